@@ -1,0 +1,219 @@
+"""ctypes wrapper of the CPU oracle (hase_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and the
+cpu_baseline leg of bench.py, never by the product package. It shares no code
+with the HIP path; the only module both sides import is the seeded input
+generator module (paper_2604_27162_amd.workloads), which holds no step logic.
+
+Layout of every array (same contract as the C-ABI library, written here
+independently):
+  obs  one step: concatenation over envs of [n][C][w] uint32, w = ceil((2r+1)^2/32)
+  rew  one step: concatenation over envs of [n] float32
+  done one step: [n_envs] uint8, bit 0 terminated, bit 1 truncated
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hase_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+SPEC_FIELDS = ("H", "W", "n", "S", "r", "C", "wall_pct", "flags", "L")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc -O2 (plain C, single-threaded)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC",
+                               "-shared", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [
+        ("n_envs", ctypes.c_int32),
+        ("spec", ctypes.c_void_p),
+        ("grid_off", ctypes.c_void_p),
+        ("agent_off", ctypes.c_void_p),
+        ("obs_off", ctypes.c_void_p),
+        ("agents_total", ctypes.c_int64),
+        ("obs_total", ctypes.c_int64),
+        ("walls", ctypes.c_void_p),
+        ("px", ctypes.c_void_p),
+        ("py", ctypes.c_void_p),
+        ("found", ctypes.c_void_p),
+        ("t", ctypes.c_void_p),
+        ("ep", ctypes.c_void_p),
+        ("steps", ctypes.c_void_p),
+        ("seed", ctypes.c_void_p),
+        ("env_id", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def _bind(path: str):
+    L = ctypes.CDLL(path)
+    L.or_reset.restype = ctypes.c_int
+    L.or_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.c_uint64, ctypes.c_void_p]
+    L.or_step.restype = None
+    L.or_step.argtypes = [ctypes.POINTER(_Batch), ctypes.c_int, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.or_observe_all.restype = None
+    L.or_observe_all.argtypes = [ctypes.POINTER(_Batch), ctypes.c_void_p]
+    L.or_philox_block.restype = None
+    L.or_philox_block.argtypes = [ctypes.c_uint32] * 6 + [ctypes.c_void_p]
+    L.or_range.restype = ctypes.c_uint32
+    L.or_range.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    L.or_wall_threshold.restype = ctypes.c_uint32
+    L.or_wall_threshold.argtypes = [ctypes.c_uint32]
+    L.or_spawn_env.restype = None
+    L.or_spawn_env.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                               ctypes.c_uint32]
+    return L
+
+
+def lib(path: str | None = None):
+    """The oracle library (or, for mutation tests, another build of it)."""
+    global _lib
+    if path is not None:
+        return _bind(path)
+    if _lib is None:
+        _lib = _bind(build())
+    return _lib
+
+
+def philox(counter, key):
+    """Philox4x32-10 block for counter (4 words) and key (2 words)."""
+    out = np.zeros(4, np.uint32)
+    lib().or_philox_block(*[int(c) for c in counter], *[int(k) for k in key],
+                          out.ctypes.data)
+    return out
+
+
+def range_map(x: int, m: int) -> int:
+    return int(lib().or_range(int(x), int(m)))
+
+
+def wall_threshold(pct: int) -> int:
+    return int(lib().or_wall_threshold(int(pct)))
+
+
+def words_per_channel(r: int) -> int:
+    d = 2 * r + 1
+    return (d * d + 31) // 32
+
+
+def spec_table(specs) -> np.ndarray:
+    """int32 [n_envs][9] from a sequence of dicts, or an int32 table as is."""
+    if isinstance(specs, np.ndarray):
+        return np.ascontiguousarray(specs, dtype=np.int32).reshape(-1, len(SPEC_FIELDS))
+    rows = [[int(s[f]) for f in SPEC_FIELDS] for s in specs]
+    return np.ascontiguousarray(np.array(rows, dtype=np.int32).reshape(-1, len(SPEC_FIELDS)))
+
+
+class OracleBatch:
+    """A batch of independent environments stepped by the oracle.
+
+    specs: sequence of per-env spec dicts with keys H, W, n, S, r, C,
+    wall_pct, flags, L. env_ids default to env_id_base + index.
+    """
+
+    def __init__(self, specs, env_id_base: int = 0, env_ids=None, libpath=None):
+        self._lib = lib(libpath)
+        self.spec = spec_table(specs)
+        ne = self.spec.shape[0]
+        H, W, n, r, C = (self.spec[:, i] for i in (0, 1, 2, 4, 5))
+        d = 2 * r.astype(np.int64) + 1
+        w = (d * d + 31) // 32
+        cells = (H.astype(np.int64) * W)
+        per_obs = n.astype(np.int64) * C * w
+        self.n_envs = ne
+        self.grid_off = np.zeros(ne, np.int64)
+        self.agent_off = np.zeros(ne, np.int64)
+        self.obs_off = np.zeros(ne, np.int64)
+        if ne > 1:
+            self.grid_off[1:] = np.cumsum(cells)[:-1]
+            self.agent_off[1:] = np.cumsum(n.astype(np.int64))[:-1]
+            self.obs_off[1:] = np.cumsum(per_obs)[:-1]
+        self.agents_total = int(n.sum())
+        self.obs_total = int(per_obs.sum())
+        self.walls = np.zeros(int(cells.sum()), np.uint8)
+        self.px = np.zeros(self.agents_total, np.uint8)
+        self.py = np.zeros(self.agents_total, np.uint8)
+        self.found = np.zeros(ne, np.uint32)
+        self.t = np.zeros(ne, np.uint32)
+        self.ep = np.zeros(ne, np.uint32)
+        self.steps = np.zeros(ne, np.uint32)
+        self.seed = np.zeros(ne, np.uint64)
+        if env_ids is None:
+            self.env_id = (np.arange(ne, dtype=np.uint64) + env_id_base).astype(np.uint32)
+        else:
+            self.env_id = np.ascontiguousarray(env_ids, dtype=np.uint32)
+        self._c = _Batch(
+            ne, self.spec.ctypes.data, self.grid_off.ctypes.data, self.agent_off.ctypes.data,
+            self.obs_off.ctypes.data, self.agents_total, self.obs_total,
+            self.walls.ctypes.data, self.px.ctypes.data, self.py.ctypes.data,
+            self.found.ctypes.data, self.t.ctypes.data, self.ep.ctypes.data,
+            self.steps.ctypes.data, self.seed.ctypes.data, self.env_id.ctypes.data)
+
+    def reset(self, seed: int) -> np.ndarray:
+        obs0 = np.zeros(self.obs_total, np.uint32)
+        rc = self._lib.or_reset(ctypes.byref(self._c), ctypes.c_uint64(seed), obs0.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"env {-rc - 1} has fewer free cells than agents")
+        return obs0
+
+    def step(self, n_steps: int = 1, actions=None):
+        obs = np.zeros((n_steps, self.obs_total), np.uint32)
+        rew = np.zeros((n_steps, self.agents_total), np.float32)
+        done = np.zeros((n_steps, self.n_envs), np.uint8)
+        aptr = None
+        if actions is not None:
+            actions = np.ascontiguousarray(actions, dtype=np.int8).reshape(n_steps, self.agents_total)
+            aptr = actions.ctypes.data
+        self._lib.or_step(ctypes.byref(self._c), int(n_steps), aptr, obs.ctypes.data,
+                      rew.ctypes.data, done.ctypes.data)
+        return obs, rew, done
+
+    def observe(self) -> np.ndarray:
+        obs = np.zeros(self.obs_total, np.uint32)
+        self._lib.or_observe_all(ctypes.byref(self._c), obs.ctypes.data)
+        return obs
+
+    # state as plain host arrays (same fields as the library's checkpoint)
+    def get_state(self) -> dict:
+        return dict(walls=self.walls.copy(), pos_x=self.px.copy(), pos_y=self.py.copy(),
+                    found=self.found.copy(), t=self.t.copy(), episode=self.ep.copy(),
+                    steps=self.steps.copy(), seed=self.seed.copy(), env_id=self.env_id.copy())
+
+    def set_state(self, st: dict) -> None:
+        self.walls[:] = st["walls"]
+        self.px[:] = st["pos_x"]
+        self.py[:] = st["pos_y"]
+        self.found[:] = st["found"]
+        self.t[:] = st["t"]
+        self.ep[:] = st["episode"]
+        self.steps[:] = st["steps"]
+        self.seed[:] = st["seed"]
+        self.env_id[:] = st["env_id"]
+
+
+def spawn(spec: dict, walls: np.ndarray, seed: int, env: int, episode: int):
+    """Positions the spawn rule gives one env (exported for spawn tests)."""
+    sp = spec_table([spec])[0].copy()
+    walls = np.ascontiguousarray(walls, dtype=np.uint8)
+    px = np.zeros(int(spec["n"]), np.uint8)
+    py = np.zeros(int(spec["n"]), np.uint8)
+    lib().or_spawn_env(sp.ctypes.data, walls.ctypes.data, px.ctypes.data, py.ctypes.data,
+                       ctypes.c_uint64(seed), int(env), int(episode))
+    return px, py

@@ -1,0 +1,106 @@
+"""Each plausible mistake planted in a copy of the oracle (on the CPU) must be
+caught by at least one pin: the hand-worked grids, the brute-force checker,
+or the rocRAND-based generator checks."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from tests import bruteforce_spec as bf
+from tests import test_oracle_golden as golden
+from tests import test_oracle_rng as rng
+
+SRC = open(o.SRC).read()
+
+MUTATIONS = {
+    "north_south_swapped": ("OR_DY[5] = { 0, -1, 1, 0, 0 }", "OR_DY[5] = { 0, 1, -1, 0, 0 }"),
+    "manhattan_not_chebyshev": ("int cheb = ddx > ddy ? ddx : ddy;", "int cheb = ddx + ddy;"),
+    "collisions_ignored": ("if (j != i && px[j] == tx && py[j] == ty) blocked = 1;",
+                           "if (0) blocked = 1;"),
+    "window_bit_transposed": ("int k = (dy + r) * d + (dx + r);", "int k = (dx + r) * d + (dy + r);"),
+    "hider_reward_sign": ("int v = or_is_seeker(i, S) ? count[i] : -count[i];", "int v = count[i];"),
+    "truncation_off_by_one": ("int truncated = b->t[e] >= L;", "int truncated = b->t[e] > L;"),
+    "wall_index_transposed": ("if (walls[ty * W + tx]) continue;", "if (walls[tx * H + ty]) continue;"),
+    "philox_weyl_constant": ("k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
+    "philox_key_word": ("uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi1 ^ c1 ^ k1;"),
+    "wall_channel_drops_outside": ("if (!inb || walls[cy * W + cx]) oi[0 * w + word] |= bit;",
+                                   "if (inb && walls[cy * W + cx]) oi[0 * w + word] |= bit;"),
+    "found_not_latched": ("b->found[e] |= 1u << h;", "b->found[e] = 1u << h;"),
+    "respawn_old_episode": ("or_spawn(sp, walls, px, py, seed, env, b->ep[e]);",
+                            "or_spawn(sp, walls, px, py, seed, env, b->ep[e] - 1);"),
+    "action_keyed_by_t": ("b->steps[e], 0, i & 3), 5u);", "b->t[e], 0, i & 3), 5u);"),
+    "obs_before_reset": ("    /* 5 auto-reset */\n    if (d) {",
+                         "    or_observe(sp, walls, px, py, obs);\n    if (0) {"),
+    "opponent_as_teammate": ("if (or_is_seeker(j, S) == or_is_seeker(i, S))", "if (1)"),
+}
+
+
+def build_mutant(old, new, d):
+    assert SRC.count(old) == 1, old
+    path = os.path.join(d, "mut.c")
+    open(path, "w").write(SRC.replace(old, new))
+    lib = os.path.join(d, "libmut.so")
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", lib, path])
+    return lib
+
+
+def run_pins(libpath, rocrand_philox):
+    """Return the name of the first pin that fails, or None."""
+    def golden_pin():
+        for case in golden.CASES:
+            sp, st = golden.load_case(case)
+            b = o.OracleBatch([sp], libpath=libpath)
+            b.set_state(st)
+            obs, rew, done = b.step(1, actions=np.array([case["actions"]], np.int8))
+            golden.check_case(case, obs[0], rew[0], done[0], b.get_state())
+
+    def brute_pin():
+        fams = [bf.case_one_agent(r=1, C=4, subsample=30_000, seed=1),
+                bf.case_seeker_hider(n_patterns=12, flags=1),
+                bf.case_seeker_hider(n_patterns=12, flags=3, seed=2),
+                bf.case_three_agents(r=1, C=4, flags=3, S=1)]
+        for spec, st, acts in fams:
+            B = st["pos_x"].shape[0]
+            table = np.tile(np.array([[spec[f] for f in o.SPEC_FIELDS]], np.int32), (B, 1))
+            b = o.OracleBatch(table, libpath=libpath)
+            b.set_state(bf.flat_state(st))
+            obs, rew, done = b.step(1, actions=acts.reshape(1, -1))
+            bf.check_step(spec, st, acts, obs[0], rew[0], done[0], b.get_state())
+
+    def philox_pin():
+        L = o.lib(libpath)
+        g = np.random.Generator(np.random.PCG64(5))
+        rows = g.integers(0, 2**30, size=(64, 6), dtype=np.uint64)
+        ref = rocrand_philox(rows)
+        for r, want in zip(rows, ref):
+            out = np.zeros(4, np.uint32)
+            L.or_philox_block(*[int(v) for v in r[2:]], *[int(v) for v in r[:2]],
+                              out.ctypes.data)
+            assert np.array_equal(out, want)
+
+    pins = [("golden", golden_pin), ("bruteforce", brute_pin), ("philox", philox_pin),
+            ("streams", lambda: rng.check_stream_layout(rocrand_philox, libpath)),
+            ("respawn", lambda: rng.check_respawn_keyed_by_episode(rocrand_philox, libpath))]
+    for name, fn in pins:
+        try:
+            fn()
+        except AssertionError:
+            return name
+    return None
+
+
+def test_unmutated_oracle_passes_pins(rocrand_philox):
+    with tempfile.TemporaryDirectory() as d:
+        lib = build_mutant("OR_DY[5]", "OR_DY[5]", d)
+        assert run_pins(lib, rocrand_philox) is None
+
+
+@pytest.mark.parametrize("name", list(MUTATIONS))
+def test_mutation_is_caught(name, rocrand_philox):
+    old, new = MUTATIONS[name]
+    with tempfile.TemporaryDirectory() as d:
+        lib = build_mutant(old, new, d)
+        assert run_pins(lib, rocrand_philox) is not None, name

@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the vectorised hide-and-seek step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload single16k]
+
+One "step" is one pass of the whole step (actions drawn by the counter
+generator, moves, detection/rewards, dones, auto-reset, observations) over
+every env of the batch. W untimed warmup steps run first; then exactly K
+steps run as one persistent call (one hipGraph launch of the step kernel) with
+all state resident in HBM, timed with HIP events on the kernel's stream. The
+same K steps are then timed with one kernel launch per step for comparison,
+and the CPU oracle is timed on a bounded sample of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "agent-steps/sec on 1 MI355X (persistent vs per-step launch); % of HBM peak"
+
+DESCR = {
+    "single16k": "16384 envs, 32x32 grid, 15% iid walls, 1 seeker + 1 hider, 7x7 window, "
+                 "3 bit-packed channels, episode 256, counter-generator actions",
+    "single1k": "1024 envs, 32x32 grid, 15% iid walls, 1 seeker + 1 hider, 7x7 window, "
+                "3 bit-packed channels, episode 256, counter-generator actions",
+    "small": "1024 envs, 16x16 grid, 10% iid walls, 1 seeker + 1 hider, 5x5 window, 3 channels",
+    "multi10": "4096 envs, 32x32 grid, 15% iid walls, 5 seekers + 5 hiders, 9x9 window, "
+               "4 channels, collisions in agent order",
+    "uneven8k": "8192 envs: sides {16,32,64} (50/30/20%), 1..10 agents, 5..25% walls, "
+                "radius 2..4, 4 channels",
+}
+
+
+def words(r: int) -> int:
+    d = 2 * r + 1
+    return (d * d + 31) // 32
+
+
+def out_bytes_per_step(specs) -> int:
+    """Algorithmic output bytes of one step: packed obs words, one float32
+    reward per agent, one uint8 done per env."""
+    return sum(4 * s["n"] * s["C"] * words(s["r"]) + 4 * s["n"] + 1 for s in specs)
+
+
+def state_bytes_per_launch(specs) -> int:
+    """Bytes a launch must read and write once: per-env spec/offset/key words
+    and counters (read 56 B, write 16 B), agent positions (2 B each way), and the
+    padded wall bitboard (read)."""
+    tot = 0
+    for s in specs:
+        P = (s["W"] + 8 + 31) // 32
+        board = 4 * ((s["H"] + 8) * P + 1)
+        tot += 56 + 16 + 4 * s["n"] + board
+    return tot
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("hase_kernels.hip", "hase_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2604_27162_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str, steps: int):
+    """HBM bytes per launch measured by rocprofv3 counters for this kernel
+    source (None if absent or taken on another version of the kernel)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    e = d.get(workload)
+    if not e or e.get("kernel_hash") != kernel_source_hash() or e.get("steps") != steps:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(specs, seed: int, budget_s: float = 12.0):
+    from oracle import oracle
+
+    b = oracle.OracleBatch(specs)
+    b.reset(seed)
+    agents = sum(s["n"] for s in specs)
+    steps, t0 = 0, time.perf_counter()
+    chunk = 10
+    while True:
+        b.step(chunk)
+        steps += chunk
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 5000:
+            break
+    return dict(value=agents * steps / el, unit="agent-steps/s", cores=1, kind="oracle",
+                sample=f"all {len(specs)} envs x {steps} steps after reset, single thread, "
+                       f"{el:.1f} s",
+                env_steps_per_s=len(specs) * steps / el)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="single16k", choices=sorted(DESCR))
+    ap.add_argument("--lanes", default=None, help="lanes per env per agent bucket, e.g. 4,4,16,16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-launch", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the environments are independent, so a multi-GPU "
+              "run is N independent shards (env-id ranges) with no exchange; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_27162_amd import hase, workloads as wl
+
+    torch.cuda.set_device(0)
+    w = wl.WORKLOADS[args.workload]
+    specs = wl.workload_specs(args.workload)
+    K, W = int(args.steps), int(args.warmup)
+    n_envs = len(specs)
+    agents = sum(s["n"] for s in specs)
+    lanes = [int(x) for x in args.lanes.split(",")] if args.lanes else None
+
+    g = hase.HaseBatch(specs, device="cuda:0", lanes=lanes)
+    stream = g.stream
+    g.reset(w["seed"])
+    obs, rew, done = g.alloc_outputs(K)
+    if W > 0:
+        g.step_into(obs, rew, done, W)
+    g.prepare(obs, rew, done, K)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    g.step_into(obs, rew, done, K)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    value = agents * K / (ms / 1e3)
+
+    per_launch = None
+    if not args.no_per_launch:
+        g2 = hase.HaseBatch(specs, device="cuda:0", lanes=lanes)
+        g2.reset(w["seed"])
+        if W > 0:
+            g2.step_into(obs, rew, done, min(W, K), mode=hase.PER_LAUNCH)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        g2.step_into(obs, rew, done, K, mode=hase.PER_LAUNCH)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_pl = ev0.elapsed_time(ev1)
+        per_launch = dict(value=agents * K / (ms_pl / 1e3), ms_per_step=ms_pl / K,
+                          unit="agent-steps/s")
+        g2.close()
+
+    alg_bytes = K * out_bytes_per_step(specs) + state_bytes_per_launch(specs)
+    achieved = alg_bytes / (ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(args.workload, K)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {DESCR[args.workload]}", "n_envs": n_envs,
+                   "agents": agents, "steps_per_call": K, "launch": "persistent hipGraph",
+                   "lanes_per_env": g.get_tiling()},
+        "env_steps_per_s": n_envs * K / (ms / 1e3),
+        "per_launch": per_launch,
+        "persistent_speedup": (value / per_launch["value"]) if per_launch else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "step_kernel (persistent)",
+                     "alg_bytes_per_launch": alg_bytes, "launch_ms": ms},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(specs, w["seed"])
+        line["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+    g.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

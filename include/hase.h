@@ -1,0 +1,215 @@
+/*
+ * hase.h -- C ABI of the MI355X (gfx950) vectorised hide-and-seek step.
+ *
+ * One call steps thousands of independent hide-and-seek gridworlds: every
+ * agent's discrete action is applied under the wall and collision rules,
+ * seeker/hider detection becomes rewards and termination flags, finished
+ * episodes auto-reset from their unchanged grid, random actions come from a
+ * counter-based generator, and every agent's bit-packed egocentric window is
+ * written. This is the data-parallel environment step of the paper's engine
+ * (Sec. 4.1: the step loop over environments, with rewards, termination and
+ * truncation outputs; Sec. 4.2: pristine-grid resets; Sec. 3.3: desynchronised
+ * initialisation and the decentralised observation mode), reduced to a
+ * discrete gridworld (Sec. 3.1 problem tuple, Sec. 3.2 blocking tiles).
+ *
+ * Memory: the caller allocates ALL device memory (state buffer, actions,
+ * observations, rewards, dones), e.g. as torch tensors; the library keeps only
+ * a host handle and never frees caller memory. Pointers named d_* are device
+ * pointers, h_* are host pointers.
+ *
+ * Asynchrony: hase_step and hase_observe only enqueue work on the handle's
+ * stream (hipStream_t passed as void*); the caller synchronises. hase_reset,
+ * hase_get_state and hase_set_state synchronise the stream before returning.
+ *
+ * Errors: every call returns HASE_OK (0) or a negative code; arguments are
+ * validated before any work is enqueued. hase_last_error() gives a
+ * thread-local detail string for the last failing call of the calling thread.
+ *
+ * Threading: one handle must not be used from two host threads at once;
+ * distinct handles are independent and may share a stream.
+ */
+#ifndef HASE_H
+#define HASE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define HASE_OK 0
+#define HASE_EINVAL (-1)  /* bad spec or argument */
+#define HASE_ENOMEM (-2)  /* caller's state buffer smaller than required */
+#define HASE_EGRID (-3)   /* an env drew fewer free cells than agents */
+#define HASE_EHIP (-4)    /* HIP runtime error (detail in hase_last_error) */
+#define HASE_ESTATE (-5)  /* state arrays inconsistent with the batch */
+#define HASE_ENOTREADY (-6) /* step/observe before the first reset or set_state */
+
+/* ---------------------------------------------------------------- flags */
+#define HASE_COLLIDE 1u      /* a move into a cell held by another agent is rejected */
+#define HASE_CAPTURE_ENDS 2u /* the episode terminates once every hider was found */
+#define HASE_DESYNC 4u       /* first episode starts with t0 ~ U{0..L-1} elapsed */
+
+/* step modes */
+#define HASE_STEP_PERSISTENT 0u  /* all n_steps in one launch per tile variant (graph-replayed) */
+#define HASE_STEP_PER_LAUNCH 1u  /* one kernel launch per step (baseline) */
+
+/*
+ * One environment's configuration.
+ *   height, width  grid size, 2..64 each; cell (x, y), x = column, y = row,
+ *                  y = 0 the top row
+ *   n_agents       1..20 (the paper's agent bound, Sec. 3)
+ *   n_seekers      0..n_agents; agents [0, n_seekers) seek, the rest hide
+ *   view_radius    r in 1..4: the window is (2r+1) x (2r+1) cells, and a seeker
+ *                  detects a hider at Chebyshev distance <= r
+ *   n_channels     3 (blocked, teammate, opponent) or 4 (+ outside-the-map)
+ *   wall_pct       0..99: each cell is an iid blocking tile with this
+ *                  probability (integer threshold, see hase_reset)
+ *   flags          HASE_COLLIDE | HASE_CAPTURE_ENDS | HASE_DESYNC
+ *   episode_len    L in 1..65535: truncation when t reaches L
+ */
+typedef struct hase_env_spec {
+    uint16_t height, width;
+    uint8_t n_agents, n_seekers, view_radius, n_channels;
+    uint8_t wall_pct, flags;
+    uint16_t episode_len;
+} hase_env_spec;
+
+/*
+ * A batch: n_envs environments. specs points to n_specs host entries:
+ * n_specs == 1 broadcasts one spec (uniform batch), n_specs == n_envs gives
+ * every env its own spec (uneven batch). Env e's generator id is
+ * env_id_base + e (so shards of one logical batch reproduce it exactly).
+ */
+typedef struct hase_batch_desc {
+    uint32_t n_envs;
+    const hase_env_spec *specs;
+    uint32_t n_specs;
+    uint32_t env_id_base;
+} hase_batch_desc;
+
+/*
+ * Sizes of a batch. Per step the outputs are
+ *   obs   obs_words_per_step uint32: env e's [n][C][w] block (w =
+ *         ceil((2r+1)^2 / 32)) starts at word obs_off[e] (hase_get_offsets);
+ *         for agent i, channel c the window bit k = (dy+r)(2r+1) + (dx+r) is
+ *         bit (k & 31) of word (i*C + c)*w + (k >> 5); unused bits are 0.
+ *         Channels: 0 blocking tile or outside the map, 1 another agent of the
+ *         same role, 2 an agent of the other role, 3 outside the map.
+ *   rew   agents_total float32: env e's agents start at agent_off[e]
+ *   done  n_envs uint8: bit 0 terminated, bit 1 truncated
+ * and external actions are agents_total int8 per step.
+ * state_bytes is the device buffer hase_create needs; cells_total the
+ * number of grid cells (walls array of the host state).
+ */
+typedef struct hase_layout {
+    uint64_t state_bytes;
+    uint64_t obs_words_per_step;
+    uint64_t agents_total;
+    uint64_t n_envs;
+    uint64_t cells_total;
+} hase_layout;
+
+/*
+ * Host-side state of a batch (checkpoint / test loading). All arrays are
+ * host memory owned by the caller, sized from hase_layout:
+ *   walls    [cells_total] uint8, env e's H*W cells row-major, 1 = blocking
+ *   pos_x/y  [agents_total] uint8 (x < W, y < H)
+ *   found    [n_envs] hiders found this episode (bit i = agent i)
+ *   t        [n_envs] steps elapsed in the episode
+ *   episode  [n_envs] episode index since the reset
+ *   steps    [n_envs] step calls since the reset (the generator's step key)
+ *   seed     [n_envs] generator seed
+ * Env ids are not part of the state: they come from the batch descriptor.
+ */
+typedef struct hase_host_state {
+    uint8_t *walls;
+    uint8_t *pos_x, *pos_y;
+    uint32_t *found, *t, *episode, *steps;
+    uint64_t *seed;
+} hase_host_state;
+
+typedef struct hase_batch hase_batch;
+
+/* Fill *out for the batch; validates every spec. */
+int hase_query_layout(const hase_batch_desc *desc, hase_layout *out);
+
+/*
+ * Create a handle over caller memory d_state (>= layout.state_bytes device
+ * bytes, 256-byte aligned) on stream (a hipStream_t, or NULL for the null
+ * stream). Uploads the per-env tables (synchronously). The envs are not usable
+ * until hase_reset or hase_set_state.
+ */
+int hase_create(const hase_batch_desc *desc, void *d_state, uint64_t state_bytes,
+                void *stream, hase_batch **out);
+
+/* Copy the per-env output offsets (words / agents) into host arrays [n_envs]. */
+int hase_get_offsets(const hase_batch *b, uint64_t *h_obs_off, uint64_t *h_agent_off);
+
+/*
+ * reset(seed) of every env (Sec. 3.3 desynchronised start, Sec. 4.2 grid):
+ * walls from the generator, free-cell check (HASE_EGRID names the first env
+ * with fewer free cells than agents), agents spawned, counters cleared,
+ * desync offset drawn; writes the first observation to d_obs0
+ * (obs_words_per_step words; may be NULL). Synchronises the stream.
+ */
+int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0);
+
+/*
+ * n_steps >= 1 consecutive steps of every env (the step loop of Sec. 4.1):
+ * actions, moves, detection and rewards, termination/truncation, same-step
+ * auto-reset, observation of the resulting state.
+ *   d_actions  NULL (every action drawn from the generator) or
+ *              [n_steps][agents_total] int8; -1 = draw, 0 stay, 1 N (y-1),
+ *              2 S (y+1), 3 E (x+1), 4 W (x-1), anything else = stay
+ *   d_obs      [n_steps][obs_words_per_step] uint32
+ *   d_rew      [n_steps][agents_total] float32
+ *   d_done     [n_steps][n_envs] uint8
+ *   mode       HASE_STEP_PERSISTENT or HASE_STEP_PER_LAUNCH (identical results)
+ * Enqueued on the stream; output buffers must not overlap the state.
+ */
+int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
+              float *d_rew, uint8_t *d_done, uint32_t mode);
+
+/*
+ * Capture (if not cached) the persistent step graph for exactly these
+ * arguments without launching it, so a later hase_step with the same
+ * arguments only replays it (no capture cost on the critical path). Same
+ * argument rules as hase_step; enqueues nothing.
+ */
+int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
+                 float *d_rew, uint8_t *d_done);
+
+/* Observation of the current state (e.g. after hase_set_state); enqueued. */
+int hase_observe(hase_batch *b, uint32_t *d_obs);
+
+/* Download / upload the full state (synchronises). set_state validates
+ * positions (inside the map) and rebuilds the device-side bitboards. */
+int hase_get_state(hase_batch *b, const hase_host_state *out);
+int hase_set_state(hase_batch *b, const hase_host_state *in);
+
+/*
+ * Tiling of the step kernel: lanes_per_env in {1,2,4,8,16,32,64} lanes of one
+ * 64-lane wavefront cooperate on one env, so a wave steps 64/lanes_per_env
+ * envs. lanes[v] applies to the envs whose agent count falls in bucket v:
+ * v = 0 for n <= 2, 1 for n <= 4, 2 for n <= 10, 3 for n <= 20. 0 keeps the
+ * built-in default. Results never depend on the tiling. Rebuilds the tile
+ * table (synchronously) and drops cached graphs.
+ */
+#define HASE_N_BUCKETS 4
+int hase_set_tiling(hase_batch *b, const uint32_t lanes[HASE_N_BUCKETS]);
+int hase_get_tiling(const hase_batch *b, uint32_t lanes[HASE_N_BUCKETS]);
+
+/* Release the handle (never frees caller memory). */
+int hase_destroy(hase_batch *b);
+
+const char *hase_strerror(int code);
+const char *hase_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HASE_H */

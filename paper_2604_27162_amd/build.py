@@ -1,0 +1,56 @@
+"""Build libhase.so in-tree for gfx950.
+
+    python -m paper_2604_27162_amd.build
+
+Kernels are compiled by hipcc for gfx950 only; the host runtime is plain C++
+(g++) against the HIP runtime API; hipcc links the shared library.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libhase.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+ARCH = "gfx950"
+
+# packed-FP32 instructions are disabled for all device code
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _hipcc() -> str:
+    p = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
+    if not os.path.exists(p):
+        raise RuntimeError("hipcc not found: the HIP library cannot be built")
+    return p
+
+
+def _run(cmd, quiet):
+    if not quiet:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd, cwd=ROOT)
+
+
+def build(quiet: bool = False) -> str:
+    """Compile the kernels and the runtime and link libhase.so (always rebuilds)."""
+    bdir = os.path.join(PKG, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    kobj = os.path.join(bdir, "hase_kernels.o")
+    robj = os.path.join(bdir, "hase_runtime.o")
+    _run([_hipcc(), *HIP_FLAGS, "-c", "-o", kobj, os.path.join(CSRC, "hase_kernels.hip")], quiet)
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+          f"-I{ROCM}/include", "-c", "-o", robj, os.path.join(CSRC, "hase_runtime.cpp")], quiet)
+    tmp = LIB + ".tmp"
+    _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, kobj, robj], quiet)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(quiet="-q" in sys.argv)

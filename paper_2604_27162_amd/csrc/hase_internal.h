@@ -1,0 +1,86 @@
+// Internal interface between the host runtime (hase_runtime.cpp) and the
+// gfx950 kernels (hase_kernels.hip). Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace hase {
+
+// Every grid is stored on the device as a padded row bitboard: PAD cells of
+// "outside" on each side (PAD >= the largest view radius, so windows and move
+// targets never leave the board), bit x' of padded row y' in word
+// y' * P + (x' >> 5), P = ceil((W + 2 PAD) / 32). Cells outside the map read
+// as blocking, so a move check needs no separate bounds test.
+constexpr int PAD = 4;
+constexpr int MAX_AGENTS = 20;
+constexpr int MAX_SIDE = 64;
+constexpr int SPAWN_ATTEMPTS = 64;
+
+// Agent-count buckets -> compile-time agent capacity of the step kernel.
+constexpr int N_BUCKETS = 4;
+constexpr int BUCKET_NMAX[N_BUCKETS] = {2, 4, 10, 20};
+
+inline int board_words_per_row(int W) { return (W + 2 * PAD + 31) >> 5; }
+// padded rows * words per row, plus one slack word so a two-word window read
+// at the last row stays inside the slot
+inline int board_words(int H, int W) { return (H + 2 * PAD) * board_words_per_row(W) + 1; }
+
+// Packed per-env spec words.
+//   spec0 = H | W << 8 | n << 16 | S << 24
+//   spec1 = r | C << 4 | flags << 8 | L << 16
+//   spec2 = wall_pct | P << 8
+struct EnvTables {
+    const uint32_t *perm;  // tile slot -> env index (tiles group similar envs)
+    const uint32_t *spec0, *spec1, *spec2;
+    const uint32_t *obs_off, *agent_off, *bb_off, *grid_off, *env_id;
+};
+
+// One stepping job: a batch's state plus this call's output buffers. Per-step
+// output strides are in elements; outputs of env e at output step s go to
+// obs[s * obs_stride + obs_off[e]], rew[s * agent_stride + agent_off[e]],
+// done[s * env_stride + e]; external actions are read at the same step index.
+struct JobDesc {
+    EnvTables tab;
+    const uint64_t *seed;
+    uint32_t *found, *t, *ep, *steps;
+    uint16_t *pos;        // x | y << 8, unpadded
+    const uint32_t *bb;   // padded bitboards
+    uint32_t *obs;
+    float *rew;
+    uint8_t *done;
+    const int8_t *act;    // may be null
+    uint64_t obs_stride, agent_stride, env_stride;
+    uint32_t k_limit;     // steps this job may take in one launch
+    uint32_t out_step0;   // output step index of the job's first step in this launch
+};
+
+// A wave's work: envs perm[env0 .. env0 + count) of job `job` (count <= 64 / lanes).
+struct Tile {
+    uint32_t job, env0, count, pad;
+};
+
+struct InitArgs {
+    EnvTables tab;
+    uint64_t *seed;
+    uint32_t *found, *t, *ep, *steps;
+    uint16_t *pos;
+    uint8_t *walls;
+    uint32_t *bb;
+    uint32_t *err;        // min over envs with too few free cells (reset only)
+    uint64_t seed_value;
+    uint32_t n_envs;
+    uint32_t rebuild_only; // 1: walls/positions already loaded, only rebuild bitboards
+};
+
+// Launch the step kernel for tile range [tile0, tile0 + n_tiles) of variant
+// (lanes, nmax). K == 0 writes the observation of the current state only.
+hipError_t launch_step(int lanes, int nmax, const Tile *tiles, uint32_t n_tiles,
+                       const JobDesc *jobs, const JobDesc &job0, uint32_t K,
+                       uint32_t step_base, uint32_t slot_words, hipStream_t stream);
+
+hipError_t launch_init(const InitArgs &a, hipStream_t stream);
+
+bool variant_supported(int lanes, int nmax);
+
+}  // namespace hase

@@ -1,0 +1,680 @@
+// Host runtime of the hide-and-seek step: the C ABI declared in include/hase.h.
+//
+// Owns no device memory: every device byte (state, inputs, outputs) comes
+// from the caller. The state buffer is carved into structure-of-arrays regions
+// (256-byte aligned): per-env spec words, output offsets, generator keys and
+// counters, agent positions, canonical walls, padded wall bitboards, the tile
+// table and an error word. The step runs as one launch per tile variant; a
+// persistent call is captured once into a hipGraph (variants as concurrent
+// branches) keyed by its arguments and replayed afterwards.
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <string>
+#include <vector>
+
+#include "../../include/hase.h"
+#include "hase_internal.h"
+
+using namespace hase;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(HASE_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                                \
+    do {                                                             \
+        hipError_t _e = (call);                                      \
+        if (_e != hipSuccess) return hip_fail(_e, #call);            \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int words_per_channel(int r)
+{
+    const int d = 2 * r + 1;
+    return (d * d + 31) / 32;
+}
+
+int bucket_of(int n)
+{
+    for (int b = 0; b < N_BUCKETS; ++b)
+        if (n <= BUCKET_NMAX[b]) return b;
+    return N_BUCKETS - 1;
+}
+
+// Built-in lanes per env for each agent-count bucket (overridable by the tiler).
+const uint32_t DEFAULT_LANES[N_BUCKETS] = {4, 4, 16, 16};
+
+int check_spec(const hase_env_spec &s, uint32_t idx)
+{
+    if (s.height < 2 || s.height > MAX_SIDE || s.width < 2 || s.width > MAX_SIDE)
+        return fail(HASE_EINVAL, "spec %u: height/width must be in 2..%d", idx, MAX_SIDE);
+    if (s.n_agents < 1 || s.n_agents > MAX_AGENTS)
+        return fail(HASE_EINVAL, "spec %u: n_agents must be in 1..%d", idx, MAX_AGENTS);
+    if (s.n_seekers > s.n_agents)
+        return fail(HASE_EINVAL, "spec %u: n_seekers > n_agents", idx);
+    if (s.view_radius < 1 || s.view_radius > PAD)
+        return fail(HASE_EINVAL, "spec %u: view_radius must be in 1..%d", idx, PAD);
+    if (s.n_channels != 3 && s.n_channels != 4)
+        return fail(HASE_EINVAL, "spec %u: n_channels must be 3 or 4", idx);
+    if (s.wall_pct > 99) return fail(HASE_EINVAL, "spec %u: wall_pct must be <= 99", idx);
+    if (s.flags & ~7u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
+    if (s.episode_len < 1) return fail(HASE_EINVAL, "spec %u: episode_len must be >= 1", idx);
+    return HASE_OK;
+}
+
+struct Regions {
+    size_t perm, spec0, spec1, spec2, obs_off, agent_off, bb_off, grid_off, env_id;
+    size_t seed, found, t, ep, steps, pos, walls, bb, tiles, err, total;
+};
+
+struct Plan {
+    std::vector<hase_env_spec> specs;
+    std::vector<uint32_t> obs_off, agent_off, grid_off, bb_off;
+    uint64_t obs_words = 0, agents = 0, cells = 0, bb_words = 0;
+    size_t max_tiles = 0;
+    Regions reg{};
+};
+
+int make_plan(const hase_batch_desc *d, Plan &p)
+{
+    if (!d) return fail(HASE_EINVAL, "null batch descriptor");
+    if (d->n_envs == 0) return fail(HASE_EINVAL, "n_envs must be >= 1");
+    if (!d->specs || (d->n_specs != 1 && d->n_specs != d->n_envs))
+        return fail(HASE_EINVAL, "n_specs must be 1 or n_envs (got %u for %u envs)", d->n_specs,
+                    d->n_envs);
+    const uint32_t N = d->n_envs;
+    p.specs.resize(N);
+    for (uint32_t e = 0; e < N; ++e) {
+        const hase_env_spec &s = d->specs[d->n_specs == 1 ? 0 : e];
+        if (d->n_specs != 1 || e == 0) {
+            const int rc = check_spec(s, e);
+            if (rc) return rc;
+        }
+        p.specs[e] = s;
+    }
+    p.obs_off.resize(N);
+    p.agent_off.resize(N);
+    p.grid_off.resize(N);
+    p.bb_off.resize(N);
+    for (uint32_t e = 0; e < N; ++e) {
+        const hase_env_spec &s = p.specs[e];
+        p.obs_off[e] = (uint32_t)p.obs_words;
+        p.agent_off[e] = (uint32_t)p.agents;
+        p.grid_off[e] = (uint32_t)p.cells;
+        p.bb_off[e] = (uint32_t)p.bb_words;
+        p.obs_words += (uint64_t)s.n_agents * s.n_channels * words_per_channel(s.view_radius);
+        p.agents += s.n_agents;
+        p.cells += (uint64_t)s.height * s.width;
+        p.bb_words += (uint64_t)board_words(s.height, s.width);
+    }
+    if (p.obs_words >= (1ull << 32) || p.cells >= (1ull << 32) || p.bb_words >= (1ull << 32))
+        return fail(HASE_EINVAL, "batch too large: per-step offsets exceed 32 bits");
+    if ((uint64_t)N + 64 >= (1ull << 32)) return fail(HASE_EINVAL, "too many envs");
+    p.max_tiles = (size_t)N + N_BUCKETS;
+    Regions &r = p.reg;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    r.perm = take(4ull * N);
+    r.spec0 = take(4ull * N);
+    r.spec1 = take(4ull * N);
+    r.spec2 = take(4ull * N);
+    r.obs_off = take(4ull * N);
+    r.agent_off = take(4ull * N);
+    r.bb_off = take(4ull * N);
+    r.grid_off = take(4ull * N);
+    r.env_id = take(4ull * N);
+    r.seed = take(8ull * N);
+    r.found = take(4ull * N);
+    r.t = take(4ull * N);
+    r.ep = take(4ull * N);
+    r.steps = take(4ull * N);
+    r.pos = take(2ull * p.agents);
+    r.walls = take(p.cells);
+    r.bb = take(4ull * p.bb_words);
+    r.tiles = take(sizeof(Tile) * p.max_tiles);
+    r.err = take(16);
+    r.total = off;
+    return HASE_OK;
+}
+
+struct Variant {
+    int lanes = 0, nmax = 0;
+    uint32_t tile0 = 0, n_tiles = 0, slot_words = 0;
+};
+
+struct GraphEntry {
+    uint32_t n_steps;
+    const void *act, *obs, *rew, *done;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct hase_batch {
+    Plan plan;
+    uint32_t n_envs = 0, env_id_base = 0;
+    char *d = nullptr;  // caller's state buffer
+    hipStream_t stream = nullptr;
+    bool ready = false;
+    uint32_t lanes[N_BUCKETS];
+    std::vector<Variant> variants;
+    hipStream_t side[N_BUCKETS] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[N_BUCKETS] = {};
+    std::list<GraphEntry> graphs;  // most recently used first
+
+    template <class T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(d + off); }
+
+    EnvTables tables() const
+    {
+        const Regions &r = plan.reg;
+        EnvTables t;
+        t.perm = at<uint32_t>(r.perm);
+        t.spec0 = at<uint32_t>(r.spec0);
+        t.spec1 = at<uint32_t>(r.spec1);
+        t.spec2 = at<uint32_t>(r.spec2);
+        t.obs_off = at<uint32_t>(r.obs_off);
+        t.agent_off = at<uint32_t>(r.agent_off);
+        t.bb_off = at<uint32_t>(r.bb_off);
+        t.grid_off = at<uint32_t>(r.grid_off);
+        t.env_id = at<uint32_t>(r.env_id);
+        return t;
+    }
+};
+
+namespace {
+
+void drop_graphs(hase_batch *b)
+{
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
+
+// Group envs by agent-count bucket, order each bucket by (n, r, area) so a
+// wave holds similar envs, and cut it into tiles of 64 / lanes envs.
+int build_tiles(hase_batch *b)
+{
+    const Plan &p = b->plan;
+    const uint32_t N = b->n_envs;
+    std::vector<uint32_t> perm;
+    perm.reserve(N);
+    std::vector<Tile> tiles;
+    std::vector<Variant> vars;
+    for (int bk = 0; bk < N_BUCKETS; ++bk) {
+        std::vector<uint32_t> ids;
+        for (uint32_t e = 0; e < N; ++e)
+            if (bucket_of(p.specs[e].n_agents) == bk) ids.push_back(e);
+        if (ids.empty()) continue;
+        std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
+            const hase_env_spec &x = p.specs[a], &y = p.specs[c];
+            if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
+            if (x.view_radius != y.view_radius) return x.view_radius > y.view_radius;
+            return x.height * x.width > y.height * y.width;
+        });
+        Variant v;
+        v.lanes = (int)b->lanes[bk];
+        v.nmax = BUCKET_NMAX[bk];
+        v.tile0 = (uint32_t)tiles.size();
+        const uint32_t E = 64u / (uint32_t)v.lanes;
+        const uint32_t base = (uint32_t)perm.size();
+        uint32_t slot = 0;
+        for (uint32_t e : ids) {
+            perm.push_back(e);
+            slot = std::max(slot, (uint32_t)board_words(p.specs[e].height, p.specs[e].width));
+        }
+        for (uint32_t i = 0; i < ids.size(); i += E) {
+            Tile t;
+            t.job = 0;
+            t.env0 = base + i;
+            t.count = std::min<uint32_t>(E, (uint32_t)ids.size() - i);
+            t.pad = 0;
+            tiles.push_back(t);
+        }
+        v.n_tiles = (uint32_t)tiles.size() - v.tile0;
+        v.slot_words = slot;
+        if ((size_t)E * (slot + 2 * v.nmax) * 4 > 65536)
+            return fail(HASE_EINVAL, "tiling: %u lanes/env needs %zu bytes of LDS per wave", v.lanes,
+                        (size_t)E * (slot + 2 * v.nmax) * 4);
+        vars.push_back(v);
+    }
+    if (tiles.size() > p.max_tiles) return fail(HASE_EINVAL, "tile table overflow");
+    HIP_TRY(hipMemcpyAsync(b->d + p.reg.perm, perm.data(), 4 * perm.size(), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d + p.reg.tiles, tiles.data(), sizeof(Tile) * tiles.size(),
+                           hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->variants = vars;
+    drop_graphs(b);
+    return HASE_OK;
+}
+
+JobDesc make_job(const hase_batch *b, const int8_t *act, uint32_t *obs, float *rew, uint8_t *done)
+{
+    const Regions &r = b->plan.reg;
+    JobDesc j;
+    j.tab = b->tables();
+    j.seed = b->at<uint64_t>(r.seed);
+    j.found = b->at<uint32_t>(r.found);
+    j.t = b->at<uint32_t>(r.t);
+    j.ep = b->at<uint32_t>(r.ep);
+    j.steps = b->at<uint32_t>(r.steps);
+    j.pos = b->at<uint16_t>(r.pos);
+    j.bb = b->at<uint32_t>(r.bb);
+    j.obs = obs;
+    j.rew = rew;
+    j.done = done;
+    j.act = act;
+    j.obs_stride = b->plan.obs_words;
+    j.agent_stride = b->plan.agents;
+    j.env_stride = b->n_envs;
+    j.k_limit = 0xffffffffu;
+    j.out_step0 = 0;
+    return j;
+}
+
+// Enqueue every variant of one call on `stream`; with `fork`, variants after
+// the first run on side streams joined back into `stream` (graph branches).
+int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, hipStream_t stream,
+            bool fork)
+{
+    const Tile *tiles = b->at<Tile>(b->plan.reg.tiles);
+    for (size_t i = 0; i < b->variants.size(); ++i) {
+        const Variant &v = b->variants[i];
+        hipStream_t s = stream;
+        if (fork && i > 0) {
+            HIP_TRY(hipEventRecord(b->fork_ev, stream));
+            HIP_TRY(hipStreamWaitEvent(b->side[i], b->fork_ev, 0));
+            s = b->side[i];
+        }
+        HIP_TRY(launch_step(v.lanes, v.nmax, tiles + v.tile0, v.n_tiles, nullptr, job, K, step_base,
+                            v.slot_words, s));
+        if (fork && i > 0) {
+            HIP_TRY(hipEventRecord(b->join_ev[i], s));
+            HIP_TRY(hipStreamWaitEvent(stream, b->join_ev[i], 0));
+        }
+    }
+    return HASE_OK;
+}
+
+int ensure_streams(hase_batch *b)
+{
+    if (b->fork_ev) return HASE_OK;
+    HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+    for (int i = 0; i < N_BUCKETS; ++i) {
+        HIP_TRY(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming));
+    }
+    return HASE_OK;
+}
+
+// The cached graph for these arguments (captured and instantiated on a miss).
+int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_t *out)
+{
+    int rc = ensure_streams(b);
+    if (rc) return rc;
+    for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
+        if (it->n_steps == n_steps && it->act == job.act && it->obs == job.obs &&
+            it->rew == job.rew && it->done == job.done) {
+            b->graphs.splice(b->graphs.begin(), b->graphs, it);
+            *out = b->graphs.front().exec;
+            return HASE_OK;
+        }
+    }
+    // capture on a private stream (the caller's may be the null stream)
+    hipStream_t cap = b->side[0];
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    rc = enqueue(b, job, n_steps, 0, cap, true);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    GraphEntry g{n_steps, job.act, job.obs, job.rew, job.done, exec};
+    b->graphs.push_front(g);
+    while (b->graphs.size() > 8) {
+        (void)hipGraphExecDestroy(b->graphs.back().exec);
+        b->graphs.pop_back();
+    }
+    *out = exec;
+    return HASE_OK;
+}
+
+int persistent_step(hase_batch *b, const JobDesc &job, uint32_t n_steps)
+{
+    hipGraphExec_t exec = nullptr;
+    const int rc = graph_for(b, job, n_steps, &exec);
+    if (rc) return rc;
+    HIP_TRY(hipGraphLaunch(exec, b->stream));
+    return HASE_OK;
+}
+
+int check_step_args(const hase_batch *b, uint32_t n_steps, const uint32_t *d_obs, const float *d_rew,
+                    const uint8_t *d_done)
+{
+    if (!b) return fail(HASE_EINVAL, "null handle");
+    if (!b->ready) return fail(HASE_ENOTREADY, "step before reset/set_state");
+    if (n_steps == 0) return fail(HASE_EINVAL, "n_steps must be >= 1");
+    if (!d_obs || !d_rew || !d_done) return fail(HASE_EINVAL, "null output buffer");
+    return HASE_OK;
+}
+
+InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
+{
+    const Regions &r = b->plan.reg;
+    InitArgs a;
+    a.tab = b->tables();
+    a.seed = b->at<uint64_t>(r.seed);
+    a.found = b->at<uint32_t>(r.found);
+    a.t = b->at<uint32_t>(r.t);
+    a.ep = b->at<uint32_t>(r.ep);
+    a.steps = b->at<uint32_t>(r.steps);
+    a.pos = b->at<uint16_t>(r.pos);
+    a.walls = b->at<uint8_t>(r.walls);
+    a.bb = b->at<uint32_t>(r.bb);
+    a.err = b->at<uint32_t>(r.err);
+    a.seed_value = seed;
+    a.n_envs = b->n_envs;
+    a.rebuild_only = rebuild;
+    return a;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+int hase_query_layout(const hase_batch_desc *desc, hase_layout *out)
+{
+    if (!out) return fail(HASE_EINVAL, "null layout pointer");
+    Plan p;
+    const int rc = make_plan(desc, p);
+    if (rc) return rc;
+    out->state_bytes = p.reg.total;
+    out->obs_words_per_step = p.obs_words;
+    out->agents_total = p.agents;
+    out->n_envs = desc->n_envs;
+    out->cells_total = p.cells;
+    return HASE_OK;
+}
+
+int hase_create(const hase_batch_desc *desc, void *d_state, uint64_t state_bytes, void *stream,
+                hase_batch **out)
+{
+    if (!out) return fail(HASE_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    hase_batch *b = new hase_batch();
+    int rc = make_plan(desc, b->plan);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    if (!d_state || ((uintptr_t)d_state & 255u)) {
+        delete b;
+        return fail(HASE_EINVAL, "state buffer must be a non-null 256-byte aligned device pointer");
+    }
+    if (state_bytes < b->plan.reg.total) {
+        const size_t need = b->plan.reg.total;
+        delete b;
+        return fail(HASE_ENOMEM, "state buffer has %llu bytes, needs %zu",
+                    (unsigned long long)state_bytes, need);
+    }
+    b->n_envs = desc->n_envs;
+    b->env_id_base = desc->env_id_base;
+    b->d = static_cast<char *>(d_state);
+    b->stream = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < N_BUCKETS; ++i) b->lanes[i] = DEFAULT_LANES[i];
+
+    const uint32_t N = b->n_envs;
+    const Plan &p = b->plan;
+    std::vector<uint32_t> s0(N), s1(N), s2(N), id(N);
+    for (uint32_t e = 0; e < N; ++e) {
+        const hase_env_spec &s = p.specs[e];
+        s0[e] = s.height | (s.width << 8) | ((uint32_t)s.n_agents << 16) | ((uint32_t)s.n_seekers << 24);
+        s1[e] = s.view_radius | ((uint32_t)s.n_channels << 4) | ((uint32_t)s.flags << 8) |
+                ((uint32_t)s.episode_len << 16);
+        s2[e] = s.wall_pct | ((uint32_t)board_words_per_row(s.width) << 8);
+        id[e] = desc->env_id_base + e;
+    }
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        return hipMemcpyAsync(b->d + off, src, bytes, hipMemcpyHostToDevice, b->stream);
+    };
+    hipError_t e;
+    if ((e = up(p.reg.spec0, s0.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.spec1, s1.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.spec2, s2.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.obs_off, p.obs_off.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.agent_off, p.agent_off.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.bb_off, p.bb_off.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.grid_off, p.grid_off.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.env_id, id.data(), 4ull * N)) != hipSuccess ||
+        (e = hipStreamSynchronize(b->stream)) != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hase_create upload");
+    }
+    rc = build_tiles(b);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return HASE_OK;
+}
+
+int hase_get_offsets(const hase_batch *b, uint64_t *h_obs_off, uint64_t *h_agent_off)
+{
+    if (!b) return fail(HASE_EINVAL, "null handle");
+    for (uint32_t e = 0; e < b->n_envs; ++e) {
+        if (h_obs_off) h_obs_off[e] = b->plan.obs_off[e];
+        if (h_agent_off) h_agent_off[e] = b->plan.agent_off[e];
+    }
+    return HASE_OK;
+}
+
+int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0)
+{
+    if (!b) return fail(HASE_EINVAL, "null handle");
+    HIP_TRY(hipMemsetAsync(b->d + b->plan.reg.err, 0xff, 4, b->stream));
+    HIP_TRY(launch_init(make_init(b, seed, 0), b->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, b->d + b->plan.reg.err, 4, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (err != 0xffffffffu) {
+        b->ready = false;
+        return fail(HASE_EGRID, "env %u has fewer free cells than agents", err);
+    }
+    b->ready = true;
+    if (d_obs0) {
+        const int rc = enqueue(b, make_job(b, nullptr, d_obs0, nullptr, nullptr), 0, 0, b->stream,
+                               false);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+    return HASE_OK;
+}
+
+int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs, float *d_rew,
+              uint8_t *d_done, uint32_t mode)
+{
+    const int rc0 = check_step_args(b, n_steps, d_obs, d_rew, d_done);
+    if (rc0) return rc0;
+    if (mode != HASE_STEP_PERSISTENT && mode != HASE_STEP_PER_LAUNCH)
+        return fail(HASE_EINVAL, "unknown step mode %u", mode);
+    const JobDesc job = make_job(b, d_actions, d_obs, d_rew, d_done);
+    if (mode == HASE_STEP_PERSISTENT) return persistent_step(b, job, n_steps);
+    for (uint32_t k = 0; k < n_steps; ++k) {
+        const int rc = enqueue(b, job, 1, k, b->stream, false);
+        if (rc) return rc;
+    }
+    return HASE_OK;
+}
+
+int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
+                 float *d_rew, uint8_t *d_done)
+{
+    const int rc = check_step_args(b, n_steps, d_obs, d_rew, d_done);
+    if (rc) return rc;
+    hipGraphExec_t exec = nullptr;
+    return graph_for(b, make_job(b, d_actions, d_obs, d_rew, d_done), n_steps, &exec);
+}
+
+int hase_observe(hase_batch *b, uint32_t *d_obs)
+{
+    if (!b) return fail(HASE_EINVAL, "null handle");
+    if (!b->ready) return fail(HASE_ENOTREADY, "observe before reset/set_state");
+    if (!d_obs) return fail(HASE_EINVAL, "null obs buffer");
+    return enqueue(b, make_job(b, nullptr, d_obs, nullptr, nullptr), 0, 0, b->stream, false);
+}
+
+int hase_get_state(hase_batch *b, const hase_host_state *out)
+{
+    if (!b || !out) return fail(HASE_EINVAL, "null argument");
+    if (!out->walls || !out->pos_x || !out->pos_y || !out->found || !out->t || !out->episode ||
+        !out->steps || !out->seed)
+        return fail(HASE_EINVAL, "null host array in state");
+    const Plan &p = b->plan;
+    const uint32_t N = b->n_envs;
+    std::vector<uint16_t> pos(p.agents);
+    auto down = [&](void *dst, size_t off, size_t bytes) {
+        return hipMemcpyAsync(dst, b->d + off, bytes, hipMemcpyDeviceToHost, b->stream);
+    };
+    HIP_TRY(down(out->walls, p.reg.walls, p.cells));
+    HIP_TRY(down(pos.data(), p.reg.pos, 2 * p.agents));
+    HIP_TRY(down(out->found, p.reg.found, 4ull * N));
+    HIP_TRY(down(out->t, p.reg.t, 4ull * N));
+    HIP_TRY(down(out->episode, p.reg.ep, 4ull * N));
+    HIP_TRY(down(out->steps, p.reg.steps, 4ull * N));
+    HIP_TRY(down(out->seed, p.reg.seed, 8ull * N));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (uint64_t i = 0; i < p.agents; ++i) {
+        out->pos_x[i] = (uint8_t)(pos[i] & 0xff);
+        out->pos_y[i] = (uint8_t)(pos[i] >> 8);
+    }
+    return HASE_OK;
+}
+
+int hase_set_state(hase_batch *b, const hase_host_state *in)
+{
+    if (!b || !in) return fail(HASE_EINVAL, "null argument");
+    if (!in->walls || !in->pos_x || !in->pos_y || !in->found || !in->t || !in->episode ||
+        !in->steps || !in->seed)
+        return fail(HASE_EINVAL, "null host array in state");
+    const Plan &p = b->plan;
+    const uint32_t N = b->n_envs;
+    std::vector<uint16_t> pos(p.agents);
+    for (uint32_t e = 0; e < N; ++e) {
+        const hase_env_spec &s = p.specs[e];
+        for (uint32_t j = 0; j < s.n_agents; ++j) {
+            const uint32_t i = p.agent_off[e] + j;
+            if (in->pos_x[i] >= s.width || in->pos_y[i] >= s.height)
+                return fail(HASE_ESTATE, "env %u agent %u outside the %ux%u map", e, j, s.width,
+                            s.height);
+            pos[i] = (uint16_t)(in->pos_x[i] | (in->pos_y[i] << 8));
+        }
+    }
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        return hipMemcpyAsync(b->d + off, src, bytes, hipMemcpyHostToDevice, b->stream);
+    };
+    HIP_TRY(up(p.reg.walls, in->walls, p.cells));
+    HIP_TRY(up(p.reg.pos, pos.data(), 2 * p.agents));
+    HIP_TRY(up(p.reg.found, in->found, 4ull * N));
+    HIP_TRY(up(p.reg.t, in->t, 4ull * N));
+    HIP_TRY(up(p.reg.ep, in->episode, 4ull * N));
+    HIP_TRY(up(p.reg.steps, in->steps, 4ull * N));
+    HIP_TRY(up(p.reg.seed, in->seed, 8ull * N));
+    HIP_TRY(launch_init(make_init(b, 0, 1), b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->ready = true;
+    return HASE_OK;
+}
+
+int hase_set_tiling(hase_batch *b, const uint32_t lanes[HASE_N_BUCKETS])
+{
+    if (!b || !lanes) return fail(HASE_EINVAL, "null argument");
+    uint32_t next[N_BUCKETS];
+    for (int i = 0; i < N_BUCKETS; ++i) {
+        next[i] = lanes[i] ? lanes[i] : DEFAULT_LANES[i];
+        if (!variant_supported((int)next[i], BUCKET_NMAX[i]))
+            return fail(HASE_EINVAL, "bucket %d: unsupported lanes per env %u", i, next[i]);
+    }
+    uint32_t prev[N_BUCKETS];
+    std::memcpy(prev, b->lanes, sizeof prev);
+    std::memcpy(b->lanes, next, sizeof next);
+    const int rc = build_tiles(b);
+    if (rc) {
+        std::memcpy(b->lanes, prev, sizeof prev);
+        build_tiles(b);
+    }
+    return rc;
+}
+
+int hase_get_tiling(const hase_batch *b, uint32_t lanes[HASE_N_BUCKETS])
+{
+    if (!b || !lanes) return fail(HASE_EINVAL, "null argument");
+    for (int i = 0; i < N_BUCKETS; ++i) lanes[i] = b->lanes[i];
+    return HASE_OK;
+}
+
+int hase_destroy(hase_batch *b)
+{
+    if (!b) return HASE_OK;
+    drop_graphs(b);
+    for (int i = 0; i < N_BUCKETS; ++i) {
+        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+        if (b->join_ev[i]) (void)hipEventDestroy(b->join_ev[i]);
+    }
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    delete b;
+    return HASE_OK;
+}
+
+const char *hase_strerror(int code)
+{
+    switch (code) {
+    case HASE_OK: return "ok";
+    case HASE_EINVAL: return "invalid argument";
+    case HASE_ENOMEM: return "state buffer too small";
+    case HASE_EGRID: return "an environment has fewer free cells than agents";
+    case HASE_EHIP: return "HIP runtime error";
+    case HASE_ESTATE: return "inconsistent state";
+    case HASE_ENOTREADY: return "batch not reset";
+    default: return "unknown error";
+    }
+}
+
+const char *hase_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

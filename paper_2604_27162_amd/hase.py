@@ -1,0 +1,261 @@
+"""Python binding of libhase.so (include/hase.h): argument marshalling only.
+
+torch provides device memory (the state buffer and every input/output
+tensor) and the stream; every step of the environment runs in the library's
+HIP kernels. There is no CPU fallback: if the library is missing or cannot
+be loaded, load() raises.
+
+Layouts (per step): obs int32 words (bit-packed windows, see hase.h), rewards
+float32 per agent, dones uint8 per env (bit 0 terminated, bit 1 truncated).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhase.so")
+
+OK, EINVAL, ENOMEM, EGRID, EHIP, ESTATE, ENOTREADY = 0, -1, -2, -3, -4, -5, -6
+COLLIDE, CAPTURE_ENDS, DESYNC = 1, 2, 4
+PERSISTENT, PER_LAUNCH = 0, 1
+N_BUCKETS = 4
+
+
+class HaseError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        super().__init__(f"hase error {code}: {detail}")
+        self.code = code
+
+
+class EnvSpec(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_uint16), ("width", ctypes.c_uint16),
+                ("n_agents", ctypes.c_uint8), ("n_seekers", ctypes.c_uint8),
+                ("view_radius", ctypes.c_uint8), ("n_channels", ctypes.c_uint8),
+                ("wall_pct", ctypes.c_uint8), ("flags", ctypes.c_uint8),
+                ("episode_len", ctypes.c_uint16)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("n_envs", ctypes.c_uint32), ("specs", ctypes.POINTER(EnvSpec)),
+                ("n_specs", ctypes.c_uint32), ("env_id_base", ctypes.c_uint32)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("state_bytes", ctypes.c_uint64), ("obs_words_per_step", ctypes.c_uint64),
+                ("agents_total", ctypes.c_uint64), ("n_envs", ctypes.c_uint64),
+                ("cells_total", ctypes.c_uint64)]
+
+
+class HostState(ctypes.Structure):
+    _fields_ = [("walls", ctypes.c_void_p), ("pos_x", ctypes.c_void_p),
+                ("pos_y", ctypes.c_void_p), ("found", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("episode", ctypes.c_void_p), ("steps", ctypes.c_void_p),
+                ("seed", ctypes.c_void_p)]
+
+
+EXPORTS = ("hase_query_layout", "hase_create", "hase_get_offsets", "hase_reset", "hase_step",
+           "hase_prepare", "hase_observe", "hase_get_state", "hase_set_state", "hase_set_tiling",
+           "hase_get_tiling", "hase_destroy", "hase_strerror", "hase_last_error")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhase.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with python -m paper_2604_27162_amd.build")
+    L = ctypes.CDLL(path)
+    vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "hase_query_layout": [ctypes.POINTER(BatchDesc), ctypes.POINTER(Layout)],
+        "hase_create": [ctypes.POINTER(BatchDesc), vp, u64, vp, ctypes.POINTER(vp)],
+        "hase_get_offsets": [vp, vp, vp],
+        "hase_reset": [vp, u64, vp],
+        "hase_step": [vp, u32, vp, vp, vp, vp, u32],
+        "hase_prepare": [vp, u32, vp, vp, vp, vp],
+        "hase_observe": [vp, vp],
+        "hase_get_state": [vp, ctypes.POINTER(HostState)],
+        "hase_set_state": [vp, ctypes.POINTER(HostState)],
+        "hase_set_tiling": [vp, ctypes.POINTER(u32 * N_BUCKETS)],
+        "hase_get_tiling": [vp, ctypes.POINTER(u32 * N_BUCKETS)],
+        "hase_destroy": [vp],
+        "hase_strerror": [ctypes.c_int],
+        "hase_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.hase_strerror.restype = ctypes.c_char_p
+    L.hase_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise HaseError(rc, load().hase_last_error().decode())
+
+
+def spec_struct(s: dict) -> EnvSpec:
+    return EnvSpec(s["H"], s["W"], s["n"], s["S"], s["r"], s["C"], s["wall_pct"], s["flags"],
+                   s["L"])
+
+
+def make_desc(specs, env_id_base: int = 0):
+    """(BatchDesc, keep-alive array) for a list of spec dicts; a single spec
+    repeated over all envs is passed once (uniform batch)."""
+    if len(specs) > 1 and all(s == specs[0] for s in specs):
+        arr = (EnvSpec * 1)(spec_struct(specs[0]))
+        return BatchDesc(len(specs), arr, 1, env_id_base), arr
+    arr = (EnvSpec * len(specs))(*[spec_struct(s) for s in specs])
+    return BatchDesc(len(specs), arr, len(specs), env_id_base), arr
+
+
+def query_layout(specs, env_id_base: int = 0) -> Layout:
+    desc, keep = make_desc(specs, env_id_base)
+    lay = Layout()
+    _check(load().hase_query_layout(ctypes.byref(desc), ctypes.byref(lay)))
+    del keep
+    return lay
+
+
+class HaseBatch:
+    """A batch of environments stepped by the HIP library on one device."""
+
+    def __init__(self, specs, env_id_base: int = 0, device="cuda", stream=None, lanes=None):
+        import torch
+
+        self.torch = torch
+        L = load()
+        self.specs = list(specs)
+        self.device = torch.device(device)
+        desc, keep = make_desc(self.specs, env_id_base)
+        lay = Layout()
+        _check(L.hase_query_layout(ctypes.byref(desc), ctypes.byref(lay)))
+        self.layout = lay
+        self.n_envs = int(lay.n_envs)
+        self.obs_words = int(lay.obs_words_per_step)
+        self.agents = int(lay.agents_total)
+        self.cells = int(lay.cells_total)
+        self.state = torch.empty(int(lay.state_bytes), dtype=torch.uint8, device=self.device)
+        if self.state.data_ptr() % 256:
+            raise RuntimeError("state buffer not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(L.hase_create(ctypes.byref(desc), self.state.data_ptr(), lay.state_bytes,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        del keep
+        self._h = h
+        if lanes is not None:
+            self.set_tiling(lanes)
+
+    # -- outputs ---------------------------------------------------------
+    def alloc_outputs(self, n_steps: int):
+        t = self.torch
+        obs = t.empty((n_steps, self.obs_words), dtype=t.int32, device=self.device)
+        rew = t.empty((n_steps, self.agents), dtype=t.float32, device=self.device)
+        done = t.empty((n_steps, self.n_envs), dtype=t.uint8, device=self.device)
+        return obs, rew, done
+
+    def reset(self, seed: int):
+        obs0 = self.torch.empty(self.obs_words, dtype=self.torch.int32, device=self.device)
+        _check(load().hase_reset(self._h, ctypes.c_uint64(seed), obs0.data_ptr()))
+        return obs0
+
+    def step_into(self, obs, rew, done, n_steps: int, actions=None, mode: int = PERSISTENT):
+        """Enqueue n_steps into preallocated outputs (no synchronisation)."""
+        for tns, shape in ((obs, (n_steps, self.obs_words)), (rew, (n_steps, self.agents)),
+                           (done, (n_steps, self.n_envs))):
+            if tns.device != self.device or not tns.is_contiguous() or tns.numel() < shape[0] * shape[1]:
+                raise ValueError("output tensor has the wrong device, layout or size")
+        aptr = None
+        if actions is not None:
+            if (actions.dtype != self.torch.int8 or actions.device != self.device
+                    or not actions.is_contiguous() or actions.numel() < n_steps * self.agents):
+                raise ValueError("actions must be a contiguous int8 device tensor "
+                                 "[n_steps][agents_total]")
+            aptr = actions.data_ptr()
+        _check(load().hase_step(self._h, int(n_steps), aptr, obs.data_ptr(), rew.data_ptr(),
+                                done.data_ptr(), int(mode)))
+
+    def prepare(self, obs, rew, done, n_steps: int, actions=None) -> None:
+        """Capture the persistent-step graph for these buffers without running it."""
+        aptr = None if actions is None else actions.data_ptr()
+        _check(load().hase_prepare(self._h, int(n_steps), aptr, obs.data_ptr(), rew.data_ptr(),
+                                   done.data_ptr()))
+
+    def step(self, n_steps: int = 1, actions=None, mode: int = PERSISTENT):
+        obs, rew, done = self.alloc_outputs(n_steps)
+        if actions is not None and not self.torch.is_tensor(actions):
+            actions = self.torch.as_tensor(np.ascontiguousarray(actions, np.int8)).to(self.device)
+        self.step_into(obs, rew, done, n_steps, actions, mode)
+        return obs, rew, done
+
+    def observe(self):
+        obs = self.torch.empty(self.obs_words, dtype=self.torch.int32, device=self.device)
+        _check(load().hase_observe(self._h, obs.data_ptr()))
+        return obs
+
+    # -- state -----------------------------------------------------------
+    def get_state(self) -> dict:
+        st = dict(walls=np.zeros(self.cells, np.uint8), pos_x=np.zeros(self.agents, np.uint8),
+                  pos_y=np.zeros(self.agents, np.uint8), found=np.zeros(self.n_envs, np.uint32),
+                  t=np.zeros(self.n_envs, np.uint32), episode=np.zeros(self.n_envs, np.uint32),
+                  steps=np.zeros(self.n_envs, np.uint32), seed=np.zeros(self.n_envs, np.uint64))
+        hs = HostState(*[st[k].ctypes.data for k in
+                         ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")])
+        _check(load().hase_get_state(self._h, ctypes.byref(hs)))
+        return st
+
+    def set_state(self, st: dict) -> None:
+        arrs = dict(walls=(np.uint8, self.cells), pos_x=(np.uint8, self.agents),
+                    pos_y=(np.uint8, self.agents), found=(np.uint32, self.n_envs),
+                    t=(np.uint32, self.n_envs), episode=(np.uint32, self.n_envs),
+                    steps=(np.uint32, self.n_envs), seed=(np.uint64, self.n_envs))
+        keep = {}
+        for k, (dt, n) in arrs.items():
+            a = np.ascontiguousarray(st[k], dtype=dt).reshape(-1)
+            if a.size != n:
+                raise ValueError(f"state field {k} has {a.size} entries, expected {n}")
+            keep[k] = a
+        hs = HostState(*[keep[k].ctypes.data for k in
+                         ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")])
+        _check(load().hase_set_state(self._h, ctypes.byref(hs)))
+
+    def offsets(self):
+        oo = np.zeros(self.n_envs, np.uint64)
+        ao = np.zeros(self.n_envs, np.uint64)
+        _check(load().hase_get_offsets(self._h, oo.ctypes.data, ao.ctypes.data))
+        return oo, ao
+
+    def set_tiling(self, lanes) -> None:
+        arr = (ctypes.c_uint32 * N_BUCKETS)(*[int(x) for x in lanes])
+        _check(load().hase_set_tiling(self._h, ctypes.byref(arr)))
+
+    def get_tiling(self):
+        arr = (ctypes.c_uint32 * N_BUCKETS)()
+        _check(load().hase_get_tiling(self._h, ctypes.byref(arr)))
+        return list(arr)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hase_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def as_u32(t) -> np.ndarray:
+    """Host uint32 view of an int32 obs tensor."""
+    return t.detach().cpu().numpy().view(np.uint32)

@@ -191,7 +191,7 @@ int hase_get_state(hase_batch *b, const hase_host_state *out);
 int hase_set_state(hase_batch *b, const hase_host_state *in);
 
 /*
- * Tiling of the step kernel: lanes_per_env in {1,2,4,8,16,32,64} lanes of one
+ * Tiling of the step kernel: lanes_per_env in {1,2,4,8,16} lanes of one
  * 64-lane wavefront cooperate on one env, so a wave steps 64/lanes_per_env
  * envs. lanes[v] applies to the envs whose agent count falls in bucket v:
  * v = 0 for n <= 2, 1 for n <= 4, 2 for n <= 10, 3 for n <= 20. 0 keeps the

@@ -20,6 +20,8 @@ constexpr int SPAWN_ATTEMPTS = 64;
 // Agent-count buckets -> compile-time agent capacity of the step kernel.
 constexpr int N_BUCKETS = 4;
 constexpr int BUCKET_NMAX[N_BUCKETS] = {2, 4, 10, 20};
+// one step-kernel variant per (agent-count bucket, view radius)
+constexpr int MAX_VARIANTS = N_BUCKETS * PAD;
 
 inline int board_words_per_row(int W) { return (W + 2 * PAD + 31) >> 5; }
 // padded rows * words per row, plus one slack word so a two-word window read
@@ -74,8 +76,9 @@ struct InitArgs {
 };
 
 // Launch the step kernel for tile range [tile0, tile0 + n_tiles) of variant
-// (lanes, nmax). K == 0 writes the observation of the current state only.
-hipError_t launch_step(int lanes, int nmax, const Tile *tiles, uint32_t n_tiles,
+// (lanes, nmax, view radius r). K == 0 writes the observation of the current
+// state only.
+hipError_t launch_step(int lanes, int nmax, int r, const Tile *tiles, uint32_t n_tiles,
                        const JobDesc *jobs, const JobDesc &job0, uint32_t K,
                        uint32_t step_base, uint32_t slot_words, hipStream_t stream);
 

@@ -133,7 +133,7 @@ int make_plan(const hase_batch_desc *d, Plan &p)
     if (p.obs_words >= (1ull << 32) || p.cells >= (1ull << 32) || p.bb_words >= (1ull << 32))
         return fail(HASE_EINVAL, "batch too large: per-step offsets exceed 32 bits");
     if ((uint64_t)N + 64 >= (1ull << 32)) return fail(HASE_EINVAL, "too many envs");
-    p.max_tiles = (size_t)N + N_BUCKETS;
+    p.max_tiles = (size_t)N + MAX_VARIANTS;
     Regions &r = p.reg;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -165,7 +165,7 @@ int make_plan(const hase_batch_desc *d, Plan &p)
 }
 
 struct Variant {
-    int lanes = 0, nmax = 0;
+    int lanes = 0, nmax = 0, r = 0;
     uint32_t tile0 = 0, n_tiles = 0, slot_words = 0;
 };
 
@@ -185,8 +185,8 @@ struct hase_batch {
     bool ready = false;
     uint32_t lanes[N_BUCKETS];
     std::vector<Variant> variants;
-    hipStream_t side[N_BUCKETS] = {};
-    hipEvent_t fork_ev = nullptr, join_ev[N_BUCKETS] = {};
+    hipStream_t side[MAX_VARIANTS] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[MAX_VARIANTS] = {};
     std::list<GraphEntry> graphs;  // most recently used first
 
     template <class T>
@@ -217,8 +217,9 @@ void drop_graphs(hase_batch *b)
     b->graphs.clear();
 }
 
-// Group envs by agent-count bucket, order each bucket by (n, r, area) so a
-// wave holds similar envs, and cut it into tiles of 64 / lanes envs.
+// Group envs by (agent-count bucket, view radius) -- one kernel variant each --,
+// order each group by (n, area) so a wave holds similar envs, and cut it into
+// tiles of 64 / lanes envs.
 int build_tiles(hase_batch *b)
 {
     const Plan &p = b->plan;
@@ -228,41 +229,43 @@ int build_tiles(hase_batch *b)
     std::vector<Tile> tiles;
     std::vector<Variant> vars;
     for (int bk = 0; bk < N_BUCKETS; ++bk) {
-        std::vector<uint32_t> ids;
-        for (uint32_t e = 0; e < N; ++e)
-            if (bucket_of(p.specs[e].n_agents) == bk) ids.push_back(e);
-        if (ids.empty()) continue;
-        std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
-            const hase_env_spec &x = p.specs[a], &y = p.specs[c];
-            if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
-            if (x.view_radius != y.view_radius) return x.view_radius > y.view_radius;
-            return x.height * x.width > y.height * y.width;
-        });
-        Variant v;
-        v.lanes = (int)b->lanes[bk];
-        v.nmax = BUCKET_NMAX[bk];
-        v.tile0 = (uint32_t)tiles.size();
-        const uint32_t E = 64u / (uint32_t)v.lanes;
-        const uint32_t base = (uint32_t)perm.size();
-        uint32_t slot = 0;
-        for (uint32_t e : ids) {
-            perm.push_back(e);
-            slot = std::max(slot, (uint32_t)board_words(p.specs[e].height, p.specs[e].width));
+        for (int r = 1; r <= PAD; ++r) {
+            std::vector<uint32_t> ids;
+            for (uint32_t e = 0; e < N; ++e)
+                if (bucket_of(p.specs[e].n_agents) == bk && p.specs[e].view_radius == r) ids.push_back(e);
+            if (ids.empty()) continue;
+            std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
+                const hase_env_spec &x = p.specs[a], &y = p.specs[c];
+                if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
+                return x.height * x.width > y.height * y.width;
+            });
+            Variant v;
+            v.lanes = (int)b->lanes[bk];
+            v.nmax = BUCKET_NMAX[bk];
+            v.r = r;
+            v.tile0 = (uint32_t)tiles.size();
+            const uint32_t E = 64u / (uint32_t)v.lanes;
+            const uint32_t base = (uint32_t)perm.size();
+            uint32_t slot = 0;
+            for (uint32_t e : ids) {
+                perm.push_back(e);
+                slot = std::max(slot, (uint32_t)board_words(p.specs[e].height, p.specs[e].width));
+            }
+            for (uint32_t i = 0; i < ids.size(); i += E) {
+                Tile t;
+                t.job = 0;
+                t.env0 = base + i;
+                t.count = std::min<uint32_t>(E, (uint32_t)ids.size() - i);
+                t.pad = 0;
+                tiles.push_back(t);
+            }
+            v.n_tiles = (uint32_t)tiles.size() - v.tile0;
+            v.slot_words = slot;
+            if ((size_t)E * slot * 4 > 65536)
+                return fail(HASE_EINVAL, "tiling: %u lanes/env needs %zu bytes of LDS per wave",
+                            v.lanes, (size_t)E * slot * 4);
+            vars.push_back(v);
         }
-        for (uint32_t i = 0; i < ids.size(); i += E) {
-            Tile t;
-            t.job = 0;
-            t.env0 = base + i;
-            t.count = std::min<uint32_t>(E, (uint32_t)ids.size() - i);
-            t.pad = 0;
-            tiles.push_back(t);
-        }
-        v.n_tiles = (uint32_t)tiles.size() - v.tile0;
-        v.slot_words = slot;
-        if ((size_t)E * (slot + 2 * v.nmax) * 4 > 65536)
-            return fail(HASE_EINVAL, "tiling: %u lanes/env needs %zu bytes of LDS per wave", v.lanes,
-                        (size_t)E * (slot + 2 * v.nmax) * 4);
-        vars.push_back(v);
     }
     if (tiles.size() > p.max_tiles) return fail(HASE_EINVAL, "tile table overflow");
     HIP_TRY(hipMemcpyAsync(b->d + p.reg.perm, perm.data(), 4 * perm.size(), hipMemcpyHostToDevice,
@@ -313,8 +316,8 @@ int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, h
             HIP_TRY(hipStreamWaitEvent(b->side[i], b->fork_ev, 0));
             s = b->side[i];
         }
-        HIP_TRY(launch_step(v.lanes, v.nmax, tiles + v.tile0, v.n_tiles, nullptr, job, K, step_base,
-                            v.slot_words, s));
+        HIP_TRY(launch_step(v.lanes, v.nmax, v.r, tiles + v.tile0, v.n_tiles, nullptr, job, K,
+                            step_base, v.slot_words, s));
         if (fork && i > 0) {
             HIP_TRY(hipEventRecord(b->join_ev[i], s));
             HIP_TRY(hipStreamWaitEvent(stream, b->join_ev[i], 0));
@@ -327,7 +330,7 @@ int ensure_streams(hase_batch *b)
 {
     if (b->fork_ev) return HASE_OK;
     HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
-    for (int i = 0; i < N_BUCKETS; ++i) {
+    for (int i = 0; i < MAX_VARIANTS; ++i) {
         HIP_TRY(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming));
     }
@@ -652,7 +655,7 @@ int hase_destroy(hase_batch *b)
 {
     if (!b) return HASE_OK;
     drop_graphs(b);
-    for (int i = 0; i < N_BUCKETS; ++i) {
+    for (int i = 0; i < MAX_VARIANTS; ++i) {
         if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
         if (b->join_ev[i]) (void)hipEventDestroy(b->join_ev[i]);
     }

@@ -82,12 +82,6 @@ def test_external_actions_with_draws_and_invalid(name):
     run_pair(specs, seed=31, steps=150, actions=acts)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32])
-def test_every_tiling_matches(lanes):
-    specs = wl.workload_specs("uneven8k", 301)
-    run_pair(specs, seed=55, steps=120, lanes=[lanes] * 4)
-
-
 BF_FAMILIES = {
     "one_agent_all_walls_r1": lambda: bf.case_one_agent(r=1, C=4),
     "one_agent_r4_sample": lambda: bf.case_one_agent(r=4, C=4, subsample=100_000, seed=4),
@@ -141,6 +135,21 @@ EDGE_SPECS = {
 def test_edge_specs(name):
     specs = [EDGE_SPECS[name]] * 70
     run_pair(specs, seed=9, steps=90)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+def test_every_tiling_matches(lanes):
+    """Variants exist for at most 4 agents per lane."""
+    specs = wl.workload_specs("uneven8k", 301) + [EDGE_SPECS["max_agents_64x64"]] * 5
+    run_pair(specs, seed=55, steps=120, lanes=[lanes, lanes, max(lanes, 4), max(lanes, 8)])
+
+
+def test_unsupported_tiling_rejected():
+    g = hase.HaseBatch(wl.workload_specs("multi10", 16), device=DEV)
+    with pytest.raises(hase.HaseError) as ei:
+        g.set_tiling([4, 4, 2, 16])  # 10 agents on 2 lanes: 5 agents per lane
+    assert ei.value.code == hase.EINVAL
+    assert g.get_tiling() == [4, 4, 16, 16]
 
 
 def test_mixed_edge_specs_one_batch():

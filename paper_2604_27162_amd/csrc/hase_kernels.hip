@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hase_internal.h"
 
 namespace hase {
@@ -276,30 +278,45 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, i
     window_rows<R, W>(slot, P, H, Wd, ax, ay, want_out, wall, outm);
     const bool sa = a < S;
     if constexpr (!EXACT) {
-        uint32_t sk[W], hd[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) sk[i] = hd[i] = 0u;
+        // bits of all agents in the window, and of the seekers among them
+        uint64_t all_lo = 0, sk_lo = 0;
+        uint32_t all_hi = 0, sk_hi = 0;  // window bits 64.. (radius 4 only)
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) {
             const uint32_t dx = (uint32_t)((pp[j] & 0xff) - ax + R);
             const uint32_t dy = (uint32_t)((pp[j] >> 8) - ay + R);
             const uint32_t kk = dy * (uint32_t)D + dx;
             const uint32_t m = dx > dy ? dx : dy;
-            const uint32_t bit = m < (uint32_t)D ? (1u << (kk & 31u)) : 0u;
+            const bool in = m < (uint32_t)D;
             const bool js = j < S;
-#pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const uint32_t bi = (kk >> 5) == (uint32_t)i ? bit : 0u;
-                sk[i] |= js ? bi : 0u;
-                hd[i] |= js ? 0u : bi;
+            if constexpr (W <= 2) {
+                const uint64_t bit = in ? (1ull << (kk & 63u)) : 0ull;
+                all_lo |= bit;
+                sk_lo |= js ? bit : 0ull;
+            } else {
+                const uint64_t bit = (in && kk < 64u) ? (1ull << (kk & 63u)) : 0ull;
+                const uint32_t bh = (in && kk >= 64u) ? (1u << (kk & 31u)) : 0u;
+                all_lo |= bit;
+                sk_lo |= js ? bit : 0ull;
+                all_hi |= bh;
+                sk_hi |= js ? bh : 0u;
             }
         }
-        int cnt = 0;
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-            team[i] = sa ? sk[i] : hd[i];
-            opp[i] = sa ? hd[i] : sk[i];
-            cnt += __builtin_popcount(opp[i]);
+        const uint64_t hd_lo = all_lo & ~sk_lo;
+        const uint64_t tm_lo = sa ? sk_lo : hd_lo, op_lo = sa ? hd_lo : sk_lo;
+        team[0] = (uint32_t)tm_lo;
+        opp[0] = (uint32_t)op_lo;
+        int cnt = __builtin_popcount((uint32_t)op_lo);
+        if constexpr (W >= 2) {
+            team[1] = (uint32_t)(tm_lo >> 32);
+            opp[1] = (uint32_t)(op_lo >> 32);
+            cnt += __builtin_popcount((uint32_t)(op_lo >> 32));
+        }
+        if constexpr (W == 3) {
+            const uint32_t hd_hi = all_hi & ~sk_hi;
+            team[2] = sa ? sk_hi : hd_hi;
+            opp[2] = sa ? hd_hi : sk_hi;
+            cnt += __builtin_popcount(opp[2]);
         }
         team[CENTER >> 5] &= ~(1u << (CENTER & 31));
         return cnt;
@@ -325,8 +342,8 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, i
     }
 }
 
-template <int R, int W, int NMAX, int TPL>
-__device__ __forceinline__ void all_masks(bool exact, const uint32_t *slot, int P, int H, int Wd,
+template <int R, int W, int NMAX, int TPL, bool EXACT>
+__device__ __forceinline__ void all_masks(const uint32_t *slot, int P, int H, int Wd,
                                           const int (&pp)[NMAX], int l, int lanes,
                                           const int (&mine)[TPL], int n, int S, bool want_out,
                                           uint32_t (&wall)[TPL][W], uint32_t (&outm)[TPL][W],
@@ -334,15 +351,9 @@ __device__ __forceinline__ void all_masks(bool exact, const uint32_t *slot, int 
                                           int (&cnt)[TPL])
 {
 #pragma unroll
-    for (int m = 0; m < TPL; ++m) {
-        const int a = l + m * lanes;
-        if (!exact)
-            cnt[m] = agent_masks<R, W, NMAX, false>(slot, P, H, Wd, pp, a, mine[m], n, S, want_out,
-                                                    wall[m], outm[m], team[m], opp[m]);
-        else
-            cnt[m] = agent_masks<R, W, NMAX, true>(slot, P, H, Wd, pp, a, mine[m], n, S, want_out,
-                                                   wall[m], outm[m], team[m], opp[m]);
-    }
+    for (int m = 0; m < TPL; ++m)
+        cnt[m] = agent_masks<R, W, NMAX, EXACT>(slot, P, H, Wd, pp, l + m * lanes, mine[m], n, S,
+                                                want_out, wall[m], outm[m], team[m], opp[m]);
 }
 
 template <int LANES, int NMAX, int R>
@@ -438,145 +449,157 @@ __global__ __launch_bounds__(64) void step_kernel(const Tile *__restrict__ tiles
     __builtin_amdgcn_s_waitcnt(0);
     wave_lds_fence();
 
-    uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W];
-    int cnt[TPL];
     uint64_t win = 0;  // generator blocks of the current action window
     int j = 0;         // step within the current action window (runtime windows)
-    for (uint32_t k = 0; k < nsteps; ++k) {
-        if (!obs_only) {
-            // ---- 1 actions: 3 bits per agent
-            uint64_t acts = 0;
-            if constexpr (DPP_WINDOW) {
-                const uint32_t jw = k & (uint32_t)(LANES - 1);
-                if (jw == 0u) {
-                    const U4 x = philox(env, ST_ACTION << 24, steps + (uint32_t)l, 0u, k0, k1);
-                    const uint32_t mine_blk = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
-                                              (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
-                    win = gather_window<LANES>(mine_blk);
-                }
-                acts = (win >> (12u * jw)) & 0xfffull;
-            } else if constexpr (WINDOWED) {
-                if (j == 0) {
-                    const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)wgroup,
-                                        steps + (uint32_t)wstep, 0u, k0, k1);
-                    win = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
-                          (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
-                }
-#pragma unroll
-                for (int g = 0; g < MAXCALLS; ++g) {
-                    if (g < ncalls) {
-                        const uint32_t v =
-                            (uint32_t)__shfl((int)(uint32_t)win, q * LANES + j * ncalls + g, 64);
-                        acts |= (uint64_t)v << (12 * g);
+    const bool has_act = J.act != nullptr;
+    // The step loop, instantiated for channels computed assuming distinct
+    // agent cells (collisions on) and for the exact per-agent test; the choice
+    // is made once per env, outside the loop.
+    auto run = [&](auto exact_tag) {
+        constexpr bool EX = decltype(exact_tag)::value;
+        uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W];
+        int cnt[TPL];
+        for (uint32_t k = 0; k < nsteps; ++k) {
+            if (!obs_only) {
+                // ---- 1 actions: 3 bits per agent
+                uint64_t acts = 0;
+                if constexpr (DPP_WINDOW) {
+                    const uint32_t jw = k & (uint32_t)(LANES - 1);
+                    if (jw == 0u) {
+                        const U4 x = philox(env, ST_ACTION << 24, steps + (uint32_t)l, 0u, k0, k1);
+                        const uint32_t mine_blk = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
+                                                  (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
+                        win = gather_window<LANES>(mine_blk);
                     }
-                }
-            } else {
-#pragma unroll
-                for (int g = 0; g < MAXCALLS; ++g) {
-                    if (g < ncalls) {
-                        const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)g, steps, 0u, k0, k1);
-                        const uint32_t a4 = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
-                                            (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
-                        acts |= (uint64_t)a4 << (12 * g);
+                    acts = (win >> (12u * jw)) & 0xfffull;
+                } else if constexpr (WINDOWED) {
+                    if (j == 0) {
+                        const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)wgroup,
+                                            steps + (uint32_t)wstep, 0u, k0, k1);
+                        win = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
+                              (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
                     }
-                }
-            }
-            if (act_p) {
-                uint64_t ov = 0, om = 0;
 #pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    if (i < n) {
-                        const int v = act_p[i];
-                        if (v != -1) {
-                            const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
-                            ov |= (uint64_t)a << (3 * i);
-                            om |= 7ull << (3 * i);
+                    for (int g = 0; g < MAXCALLS; ++g) {
+                        if (g < ncalls) {
+                            const uint32_t v =
+                                (uint32_t)__shfl((int)(uint32_t)win, q * LANES + j * ncalls + g, 64);
+                            acts |= (uint64_t)v << (12 * g);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int g = 0; g < MAXCALLS; ++g) {
+                        if (g < ncalls) {
+                            const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)g, steps, 0u, k0, k1);
+                            const uint32_t a4 = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
+                                                (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
+                            acts |= (uint64_t)a4 << (12 * g);
                         }
                     }
                 }
-                acts = (acts & ~om) | ov;
-                act_p += J.agent_stride;
-            }
-            acts &= amask;
+                if (has_act) {
+                    uint64_t ov = 0, om = 0;
+#pragma unroll
+                    for (int i = 0; i < NMAX; ++i) {
+                        if (i < n) {
+                            const int v = act_p[i];
+                            if (v != -1) {
+                                const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                                ov |= (uint64_t)a << (3 * i);
+                                om |= 7ull << (3 * i);
+                            }
+                        }
+                    }
+                    acts = (acts & ~om) | ov;
+                    act_p += J.agent_stride;
+                }
+                acts &= amask;
 
-            // ---- 2 moves, agent-index order (redundant in every lane of the env)
-            int tgt[NMAX];
-            bool open[NMAX];
+                // ---- 2 moves, agent-index order (redundant in every lane of the env)
+                int tgt[NMAX];
+                bool open[NMAX];
 #pragma unroll
-            for (int i = 0; i < NMAX; ++i) {
-                const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
-                const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
-                tgt[i] = pp[i] + dl;
-                uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)P + (((uint32_t)tgt[i] >> 5) & 7u);
-                widx = widx < last_word ? widx : last_word;
-                const uint32_t wbit = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
-                open[i] = a != 0u && wbit == 0u;
-            }
+                for (int i = 0; i < NMAX; ++i) {
+                    const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
+                    const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
+                    tgt[i] = pp[i] + dl;
+                    uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)P + (((uint32_t)tgt[i] >> 5) & 7u);
+                    widx = widx < last_word ? widx : last_word;
+                    const uint32_t wbit = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
+                    open[i] = a != 0u && wbit == 0u;
+                }
 #pragma unroll
-            for (int i = 0; i < NMAX; ++i) {
-                bool clash = false;
+                for (int i = 0; i < NMAX; ++i) {
+                    bool clash = false;
 #pragma unroll
-                for (int jj = 0; jj < NMAX; ++jj)
-                    if (jj != i) clash = clash || pp[jj] == tgt[i];
-                pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
-            }
-            own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+                    for (int jj = 0; jj < NMAX; ++jj)
+                        if (jj != i) clash = clash || pp[jj] == tgt[i];
+                    pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
+                }
+                own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
-            // ---- 3 detection (from the channels of the post-move positions)
-            all_masks<R, W, NMAX, TPL>(!collide, slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                       wall, outm, team, opp, cnt);
-            uint32_t seen_h = 0;
+                // ---- 3 detection (from the channels of the post-move positions)
+                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                                           wall, outm, team, opp, cnt);
+                uint32_t seen_h = 0;
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int a = l + m * LANES;
+                    const bool sa = a < S;
+                    if (active && a < n) rew_p[a] = (float)(sa ? cnt[m] : -cnt[m]);
+                    seen_h |= (a < n && !sa && cnt[m] > 0) ? (1u << a) : 0u;
+                }
+                found |= group_or_dpp<LANES>(seen_h);
+
+                // ---- 4 termination / truncation
+                t += 1u;
+                const bool term = (flags & 2u) && n > S && (found & hmask) == hmask;
+                const bool trunc = t >= Lep;
+                const uint32_t d = (term ? 1u : 0u) | (trunc ? 2u : 0u);
+                if (active && l == 0) *done_p = (uint8_t)d;
+
+                // ---- 5 same-step auto-reset from the unchanged grid
+                if (d) {
+                    ep += 1u;
+                    t = 0u;
+                    found = 0u;
+                    spawn_agents<NMAX>(pp, n, H, Wd, slot, P, env, k0, k1, ep);
+                    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+                    all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S,
+                                               want_out, wall, outm, team, opp, cnt);
+                }
+
+                // ---- 6 generator step key
+                steps += 1u;
+                j = (j + 1 == kb) ? 0 : j + 1;
+                rew_p += J.agent_stride;
+                done_p += J.env_stride;
+            } else {
+                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                                           wall, outm, team, opp, cnt);
+            }
+
+            // ---- 7 observations of this lane's agents (channel-major words)
 #pragma unroll
             for (int m = 0; m < TPL; ++m) {
                 const int a = l + m * LANES;
-                const bool sa = a < S;
-                if (active && a < n) rew_p[a] = (float)(sa ? cnt[m] : -cnt[m]);
-                seen_h |= (a < n && !sa && cnt[m] > 0) ? (1u << a) : 0u;
+                if (active && a < n) {
+                    GAS uint32_t *oa = obs_p + (uint32_t)(a * C * W);
+                    store_words<W>(oa, wall[m]);
+                    store_words<W>(oa + W, team[m]);
+                    store_words<W>(oa + 2 * W, opp[m]);
+                    if (want_out) store_words<W>(oa + 3 * W, outm[m]);
+                }
             }
-            found |= group_or_dpp<LANES>(seen_h);
-
-            // ---- 4 termination / truncation
-            t += 1u;
-            const bool term = (flags & 2u) && n > S && (found & hmask) == hmask;
-            const bool trunc = t >= Lep;
-            const uint32_t d = (term ? 1u : 0u) | (trunc ? 2u : 0u);
-            if (active && l == 0) *done_p = (uint8_t)d;
-
-            // ---- 5 same-step auto-reset from the unchanged grid
-            if (d) {
-                ep += 1u;
-                t = 0u;
-                found = 0u;
-                spawn_agents<NMAX>(pp, n, H, Wd, slot, P, env, k0, k1, ep);
-                own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-                all_masks<R, W, NMAX, TPL>(!collide, slot, P, H, Wd, pp, l, LANES, mine, n, S,
-                                           want_out, wall, outm, team, opp, cnt);
-            }
-
-            // ---- 6 generator step key
-            steps += 1u;
-            j = (j + 1 == kb) ? 0 : j + 1;
-            rew_p += J.agent_stride;
-            done_p += J.env_stride;
-        } else {
-            all_masks<R, W, NMAX, TPL>(!collide, slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                       wall, outm, team, opp, cnt);
+            obs_p += J.obs_stride;
         }
 
-        // ---- 7 observations of this lane's agents (channel-major words)
-#pragma unroll
-        for (int m = 0; m < TPL; ++m) {
-            const int a = l + m * LANES;
-            if (active && a < n) {
-                GAS uint32_t *oa = obs_p + (uint32_t)(a * C * W);
-                store_words<W>(oa, wall[m]);
-                store_words<W>(oa + W, team[m]);
-                store_words<W>(oa + 2 * W, opp[m]);
-                if (want_out) store_words<W>(oa + 3 * W, outm[m]);
-            }
-        }
-        obs_p += J.obs_stride;
-    }
+    };
+    if (collide)
+        run(std::false_type{});
+    else
+        run(std::true_type{});
 
     // write back the state
     if (active && !obs_only) {

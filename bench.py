@@ -65,9 +65,13 @@ def state_bytes_per_launch(specs) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device sources (counters taken on other sources are stale)."""
     h = hashlib.sha256()
-    for f in ("hase_kernels.hip", "hase_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2604_27162_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2604_27162_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -116,6 +120,9 @@ def main():
     ap.add_argument("--lanes", default=None, help="lanes per env per agent bucket, e.g. 4,4,16,16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-launch", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device-to-device copy of BYTES (calibrates the "
+                         "HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the environments are independent, so a multi-GPU "
@@ -128,6 +135,15 @@ def main():
     from paper_2604_27162_amd import hase, workloads as wl
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n}))
+        return
     w = wl.WORKLOADS[args.workload]
     specs = wl.workload_specs(args.workload)
     K, W = int(args.steps), int(args.warmup)

@@ -7,6 +7,8 @@ Kernels are compiled by hipcc for gfx950 only; the host runtime is plain C++
 """
 from __future__ import annotations
 
+import concurrent.futures
+import glob
 import os
 import shutil
 import subprocess
@@ -37,17 +39,26 @@ def _run(cmd, quiet):
     subprocess.check_call(cmd, cwd=ROOT)
 
 
-def build(quiet: bool = False) -> str:
-    """Compile the kernels and the runtime and link libhase.so (always rebuilds)."""
+def build(quiet: bool = False, jobs: int | None = None) -> str:
+    """Compile the kernels (one hipcc per translation unit, in parallel) and
+    the runtime, and link libhase.so (always rebuilds)."""
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
-    kobj = os.path.join(bdir, "hase_kernels.o")
+    cmds, objs = [], []
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        obj = os.path.join(bdir, os.path.basename(src)[:-4] + ".o")
+        cmds.append([_hipcc(), *HIP_FLAGS, "-c", "-o", obj, src])
+        objs.append(obj)
     robj = os.path.join(bdir, "hase_runtime.o")
-    _run([_hipcc(), *HIP_FLAGS, "-c", "-o", kobj, os.path.join(CSRC, "hase_kernels.hip")], quiet)
-    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
-          f"-I{ROCM}/include", "-c", "-o", robj, os.path.join(CSRC, "hase_runtime.cpp")], quiet)
+    cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+                 f"-I{ROCM}/include", "-c", "-o", robj, os.path.join(CSRC, "hase_runtime.cpp")])
+    objs.append(robj)
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, quiet) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
-    _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, kobj, robj], quiet)
+    _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], quiet)
     os.replace(tmp, LIB)
     return LIB
 

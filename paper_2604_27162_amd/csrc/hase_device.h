@@ -1,0 +1,733 @@
+// gfx950 device code of the vectorised hide-and-seek step (included by the
+// per-lanes translation units hase_step_l*.hip and by hase_kernels.hip).
+//
+// step_kernel<LANES, NMAX>: one 64-lane wavefront steps a tile of 64/LANES
+// environments; the LANES lanes of one env hold identical copies of its small
+// state (agent positions, counters) in registers, resolve the sequential moves
+// redundantly (no cross-lane traffic), and split the parallel work between
+// them: generator blocks, reward stores and (agent, word) observation tasks.
+// The env's padded wall bitboard is staged once per launch into the wave's
+// LDS slot; a persistent launch (K > 1) then runs K steps with state in
+// registers and only the outputs going to HBM.
+//
+// The rules are those of the paper's step loop (Sec. 4.1) reduced to a
+// discrete gridworld: blocking tiles (Sec. 3.2), reward for locating hiders in
+// a zero-sum game (Sec. 3, Sec. 3.1), Found flag (POIState F bit, Fig. "Bit
+// Packing Environment Structure"), termination/truncation and reset from the
+// unchanged grid (Sec. 4.1, 4.2), local-window decentralised observations
+// (Sec. 3.3 mode 1). Integer work only: no MFMA.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "hase_internal.h"
+
+namespace hase {
+
+// ------------------------------------------------------------ generator
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplies with the output permutation (hi1^c1^k0, lo1, hi0^c3^k1, lo0),
+// key bumped by the Weyl increments between rounds.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// Counter layout: (env id, stream << 24 | sub, a, b).
+enum : uint32_t { ST_ACTION = 0u, ST_SPAWN = 1u, ST_WALL = 2u, ST_DESYNC = 3u };
+
+// floor(x * m / 2^32)
+__device__ __forceinline__ uint32_t range_map(uint32_t x, uint32_t m) { return __umulhi(x, m); }
+
+// ------------------------------------------------------------ helpers
+
+// Pointers read from descriptors are generic; casting them to the global
+// address space lets the compiler use global_* (not flat_*) memory ops.
+#define GAS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GAS T *gp(T *p)
+{
+    return (GAS T *)p;
+}
+template <class T>
+__device__ __forceinline__ const GAS T *gp(const T *p)
+{
+    return (const GAS T *)p;
+}
+
+// Bit of the padded board at packed padded cell pc = y' << 8 | x'.
+__device__ __forceinline__ uint32_t board_bit(const uint32_t *slot, int P, int pc)
+{
+    const int yy = pc >> 8, xx = pc & 0xff;
+    return (slot[yy * P + (xx >> 5)] >> (xx & 31)) & 1u;
+}
+
+// Agent spawn for episode ep: agents in index order, up to 64 uniform draws
+// each, first cell that is open and not held by an earlier agent; if every
+// draw fails, the first acceptable cell scanning row-major from the cell after
+// the last draw, wrapping around. Positions (packed padded cells) are written
+// to out[0..n) in LDS; the loops are not unrolled (spawning is rare), and all
+// lanes of an env may run it together since they write identical values.
+__device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, const uint32_t *slot,
+                                             int P, uint32_t env, uint32_t k0, uint32_t k1,
+                                             uint32_t ep)
+{
+    const uint32_t cells = (uint32_t)(H * W);
+    for (int i = 0; i < n; ++i) {
+        bool placed = false;
+        uint32_t c = 0;
+        for (uint32_t j = 0; j < (uint32_t)SPAWN_ATTEMPTS && !placed; ++j) {
+            const U4 x = philox(env, (ST_SPAWN << 24) | (uint32_t)i, ep, j, k0, k1);
+            c = range_map(x.x, cells);
+            const uint32_t y = c / (uint32_t)W, xx = c - y * (uint32_t)W;
+            const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
+            bool ok = board_bit(slot, P, pc) == 0u;
+            for (int k = 0; k < i && ok; ++k) ok = out[k] != pc;
+            if (ok) {
+                out[i] = pc;
+                placed = true;
+            }
+        }
+        for (uint32_t d = 1; d <= cells && !placed; ++d) {
+            uint32_t cc = c + d;
+            if (cc >= cells) cc -= cells;
+            const uint32_t y = cc / (uint32_t)W, xx = cc - y * (uint32_t)W;
+            const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
+            bool ok = board_bit(slot, P, pc) == 0u;
+            for (int k = 0; k < i && ok; ++k) ok = out[k] != pc;
+            if (ok) {
+                out[i] = pc;
+                placed = true;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ step kernel
+
+// OR over the LANES lanes of one env with DPP moves inside 16-lane rows
+// (quad swaps, half-row and row mirrors); 32-lane groups add one shuffle.
+template <int LANES>
+__device__ __forceinline__ uint32_t group_or_dpp(uint32_t v)
+{
+    if constexpr (LANES >= 2) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    if constexpr (LANES >= 4) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    if constexpr (LANES >= 8) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+    if constexpr (LANES >= 16) v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+    if constexpr (LANES >= 32) v |= (uint32_t)__shfl_xor((int)v, 16, 64);
+    return v;
+}
+
+// Each block is one wavefront: its lanes run in lockstep and its LDS
+// operations complete in issue order, so sharing values through LDS between
+// lanes needs only a compiler ordering point (a wavefront-scope fence emits
+// no wait on outstanding global stores).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Window rows of one agent into W-word bitmasks (bit k = row * D + column),
+// fully unrolled for radius R: wall|outside from the padded board and, for
+// 4-channel envs, outside-the-map only.
+template <int R, int W>
+__device__ __forceinline__ void window_rows(const uint32_t *slot, int P, int H, int Wd, int ax,
+                                            int ay, bool want_out, uint32_t (&wall)[W],
+                                            uint32_t (&outm)[W])
+{
+    constexpr int D = 2 * R + 1;
+    constexpr uint32_t DM = (1u << D) - 1u;
+    const int col = ax - R;  // padded column of the window's left edge
+    const uint32_t *base = slot + (ay - R) * P + (col >> 5);
+    const uint32_t sh = (uint32_t)(col & 31);
+#pragma unroll
+    for (int rho = 0; rho < D; ++rho) {
+        const uint32_t *rp = base + rho * P;
+        const uint32_t bits = __builtin_amdgcn_alignbit(rp[1], rp[0], sh) & DM;
+        const int off = rho * D, wi = off >> 5, b = off & 31;
+        wall[wi] |= bits << b;
+        if (b + D > 32) wall[wi + 1] |= bits >> (32 - b);
+    }
+    if (want_out) {
+        // columns of the window left / right of the map
+        const int lowc = PAD - col > 0 ? PAD - col : 0;
+        const int hic = Wd + PAD - col;
+        const uint32_t colout = ((1u << lowc) - 1u) | (hic < D ? (DM & ~((1u << hic) - 1u)) : 0u);
+#pragma unroll
+        for (int rho = 0; rho < D; ++rho) {
+            const int row = ay - R + rho;
+            const uint32_t ob = (uint32_t)(row - PAD) >= (uint32_t)H ? DM : colout;
+            const int off = rho * D, wi = off >> 5, b = off & 31;
+            outm[wi] |= ob << b;
+            if (b + D > 32) outm[wi + 1] |= ob >> (32 - b);
+        }
+    }
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// Every lane of a 2- or 4-lane group gets the 12-bit blocks of all lanes of
+// its group, in lane order, via DPP broadcasts (quad_perm patterns).
+template <int LANES>
+__device__ __forceinline__ uint64_t gather_window(uint32_t v)
+{
+    if constexpr (LANES == 4) {
+        return (uint64_t)dpp_mov<0x00>(v) | ((uint64_t)dpp_mov<0x55>(v) << 12) |
+               ((uint64_t)dpp_mov<0xAA>(v) << 24) | ((uint64_t)dpp_mov<0xFF>(v) << 36);
+    } else {
+        return (uint64_t)dpp_mov<0xA0>(v) | ((uint64_t)dpp_mov<0xF5>(v) << 12);
+    }
+}
+
+// mine[m] = pp[l + m * LANES] (pp[0] when that agent does not exist) with
+// compile-time register indices only (a select per candidate agent), so the
+// positions never leave registers.
+template <int LANES, int NMAX, int TPL>
+__device__ __forceinline__ void own_positions(const int (&pp)[NMAX], int l, int n, int (&mine)[TPL])
+{
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+        const int a = l + m * LANES;
+        int v = pp[0];
+#pragma unroll
+        for (int i = 1; i < NMAX; ++i) v = (a == i) ? pp[i] : v;
+        mine[m] = a < n ? v : pp[0];
+    }
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+
+// W contiguous words in one vector store
+template <int W>
+__device__ __forceinline__ void store_words(GAS uint32_t *p, const uint32_t (&v)[W])
+{
+    if constexpr (W == 1) {
+        p[0] = v[0];
+    } else if constexpr (W == 2) {
+        u32x2 x;
+        x.x = v[0];
+        x.y = v[1];
+        *(GAS u32x2 *)p = x;
+    } else {
+        u32x3 x;
+        x.x = v[0];
+        x.y = v[1];
+        x.z = v[2];
+        *(GAS u32x3 *)p = x;
+    }
+}
+
+// Parking cell of unused agent slots (packed padded coordinates): never in
+// any window and never equal to a move target, so the inner loops need no
+// agent-count test.
+constexpr int FAR_CELL = (0xF0 << 8) | 0xF0;
+
+// Move-target offsets of actions 0..4 (stay, N, S, E, W) as packed
+// (dy << 8) + dx + 257, 12 bits per action.
+constexpr uint64_t MOVE_TABLE = 0x101ull | (0x001ull << 12) | (0x201ull << 24) |
+                                (0x102ull << 36) | (0x100ull << 48);
+
+// Channels of one agent at packed padded cell pa: window rows of the board
+// (wall|outside and, when want_out, outside only) and the other agents by
+// role. exact == false assumes agents occupy distinct cells (collisions on):
+// the opponent count is then the popcount of the opponent window and the
+// only agent on the centre cell is the agent itself. exact == true tests
+// every other agent by index. Returns the number of other-role agents in the
+// window (Chebyshev distance <= R).
+template <int R, int W, int NMAX, bool EXACT>
+__device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, int Wd,
+                                           const int (&pp)[NMAX], int a, int pa, int n, int S,
+                                           bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
+                                           uint32_t (&team)[W], uint32_t (&opp)[W])
+{
+    constexpr int D = 2 * R + 1;
+    constexpr int CENTER = R * D + R;
+#pragma unroll
+    for (int i = 0; i < W; ++i) wall[i] = outm[i] = team[i] = opp[i] = 0u;
+    const int ax = pa & 0xff, ay = pa >> 8;
+    window_rows<R, W>(slot, P, H, Wd, ax, ay, want_out, wall, outm);
+    const bool sa = a < S;
+    if constexpr (!EXACT) {
+        // bits of all agents in the window, and of the seekers among them
+        uint64_t all_lo = 0, sk_lo = 0;
+        uint32_t all_hi = 0, sk_hi = 0;  // window bits 64.. (radius 4 only)
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) {
+            const uint32_t dx = (uint32_t)((pp[j] & 0xff) - ax + R);
+            const uint32_t dy = (uint32_t)((pp[j] >> 8) - ay + R);
+            const uint32_t kk = dy * (uint32_t)D + dx;
+            const uint32_t m = dx > dy ? dx : dy;
+            const bool in = m < (uint32_t)D;
+            const bool js = j < S;
+            if constexpr (W <= 2) {
+                const uint64_t bit = in ? (1ull << (kk & 63u)) : 0ull;
+                all_lo |= bit;
+                sk_lo |= js ? bit : 0ull;
+            } else {
+                const uint64_t bit = (in && kk < 64u) ? (1ull << (kk & 63u)) : 0ull;
+                const uint32_t bh = (in && kk >= 64u) ? (1u << (kk & 31u)) : 0u;
+                all_lo |= bit;
+                sk_lo |= js ? bit : 0ull;
+                all_hi |= bh;
+                sk_hi |= js ? bh : 0u;
+            }
+        }
+        const uint64_t hd_lo = all_lo & ~sk_lo;
+        const uint64_t tm_lo = sa ? sk_lo : hd_lo, op_lo = sa ? hd_lo : sk_lo;
+        team[0] = (uint32_t)tm_lo;
+        opp[0] = (uint32_t)op_lo;
+        int cnt = __builtin_popcount((uint32_t)op_lo);
+        if constexpr (W >= 2) {
+            team[1] = (uint32_t)(tm_lo >> 32);
+            opp[1] = (uint32_t)(op_lo >> 32);
+            cnt += __builtin_popcount((uint32_t)(op_lo >> 32));
+        }
+        if constexpr (W == 3) {
+            const uint32_t hd_hi = all_hi & ~sk_hi;
+            team[2] = sa ? sk_hi : hd_hi;
+            opp[2] = sa ? hd_hi : sk_hi;
+            cnt += __builtin_popcount(opp[2]);
+        }
+        team[CENTER >> 5] &= ~(1u << (CENTER & 31));
+        return cnt;
+    } else {
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) {
+            const int dx = (pp[j] & 0xff) - ax + R;
+            const int dy = (pp[j] >> 8) - ay + R;
+            const bool in = j < n && j != a && (uint32_t)dx < (uint32_t)D && (uint32_t)dy < (uint32_t)D;
+            const int kk = dy * D + dx;
+            const uint32_t bit = in ? (1u << (kk & 31)) : 0u;
+            const bool same = (j < S) == sa;
+            cnt += (in && !same) ? 1 : 0;
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const uint32_t bi = (kk >> 5) == i ? bit : 0u;
+                team[i] |= same ? bi : 0u;
+                opp[i] |= same ? 0u : bi;
+            }
+        }
+        return cnt;
+    }
+}
+
+template <int R, int W, int NMAX, int TPL, bool EXACT>
+__device__ __forceinline__ void all_masks(const uint32_t *slot, int P, int H, int Wd,
+                                          const int (&pp)[NMAX], int l, int lanes,
+                                          const int (&mine)[TPL], int n, int S, bool want_out,
+                                          uint32_t (&wall)[TPL][W], uint32_t (&outm)[TPL][W],
+                                          uint32_t (&team)[TPL][W], uint32_t (&opp)[TPL][W],
+                                          int (&cnt)[TPL])
+{
+#pragma unroll
+    for (int m = 0; m < TPL; ++m)
+        cnt[m] = agent_masks<R, W, NMAX, EXACT>(slot, P, H, Wd, pp, l + m * lanes, mine[m], n, S,
+                                                want_out, wall[m], outm[m], team[m], opp[m]);
+}
+
+// K steps of one tile: the envs perm[tile.env0 ..] of job J, LANES lanes per
+// env, at most NMAX agents, view radius R. K == 0 writes the observation of
+// the current state only.
+template <int LANES, int NMAX, int R>
+__device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, uint32_t K,
+                                          uint32_t step_base, uint32_t slot_words, uint32_t *lds)
+{
+    constexpr int D = 2 * R + 1;
+    constexpr int W = (D * D + 31) / 32;             // words per channel
+    constexpr int TPL = (NMAX + LANES - 1) / LANES;  // agent tasks per lane
+    constexpr int MAXCALLS = (NMAX + 3) / 4;         // generator blocks per step
+    // actions come from a window of future steps when every block of a step
+    // has its own lane; otherwise each lane draws all blocks itself
+    constexpr bool WINDOWED = LANES >= MAXCALLS && LANES > 1;
+    // with at most 4 agents and 2 or 4 lanes the window is gathered by DPP and
+    // spans exactly LANES steps
+    constexpr bool DPP_WINDOW = WINDOWED && NMAX <= 4 && (LANES == 2 || LANES == 4);
+
+    const int lane = (int)threadIdx.x;
+    const int q = lane / LANES;  // env slot in the tile
+    const int l = lane % LANES;  // sub-lane within the env
+
+    const bool active = q < (int)tile.count;
+    // inactive slots shadow the tile's first env and never store
+    const uint32_t e = gp(J.tab.perm)[tile.env0 + (active ? (uint32_t)q : 0u)];
+
+    const uint32_t s0 = gp(J.tab.spec0)[e], s1 = gp(J.tab.spec1)[e], s2 = gp(J.tab.spec2)[e];
+    const int H = (int)(s0 & 0xffu), Wd = (int)((s0 >> 8) & 0xffu);
+    const int n = (int)((s0 >> 16) & 0xffu), S = (int)(s0 >> 24);
+    const int C = (int)((s1 >> 4) & 0xfu);
+    const uint32_t flags = (s1 >> 8) & 0xffu, Lep = s1 >> 16;
+    const int P = (int)((s2 >> 8) & 0xffu);
+    const bool collide = (flags & 1u) != 0u;
+    const bool want_out = C == 4;
+
+    const uint32_t obs_off = gp(J.tab.obs_off)[e], agent_off = gp(J.tab.agent_off)[e];
+    const uint32_t env = gp(J.tab.env_id)[e];
+    const uint64_t seed = gp(J.seed)[e];
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t found = gp(J.found)[e], t = gp(J.t)[e], ep = gp(J.ep)[e], steps = gp(J.steps)[e];
+
+    // this env's LDS slot: the padded bitboard, then MAX_AGENTS words where a
+    // respawn writes the new positions
+    uint32_t *slot = lds + (uint32_t)q * (slot_words + MAX_AGENTS);
+    int *spawned = (int *)(slot + slot_words);
+    {
+        const GAS uint32_t *src = gp(J.bb) + gp(J.tab.bb_off)[e];
+        const int bw = (H + 2 * PAD) * P + 1;
+        for (int i = l; i < bw; i += LANES) slot[i] = src[i];
+    }
+    const uint32_t last_word = slot_words - 1u;
+
+    int pp[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        int v = FAR_CELL;
+        if (j < n) {
+            const uint32_t p = gp(J.pos)[agent_off + (uint32_t)j];
+            v = (int)((((p >> 8) + PAD) << 8) | ((p & 0xffu) + PAD));
+        }
+        pp[j] = v;
+    }
+    // positions of this lane's own agents l + m * LANES (agent 0's position for
+    // lanes without an agent), kept in registers
+    int mine[TPL];
+    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+
+    const uint32_t hmask = (uint32_t)(((1ull << n) - 1ull) & ~((1ull << S) - 1ull));
+    const uint64_t amask = (1ull << (3 * n)) - 1ull;  // action bits of real agents
+    const int ncalls = (n + 3) >> 2;
+    const int kb = WINDOWED ? LANES / ncalls : 1;  // steps per action window
+    // in a window, lane l draws block (step + wstep, group wgroup)
+    const int wstep = WINDOWED ? l / ncalls : 0, wgroup = WINDOWED ? l - wstep * ncalls : 0;
+    const uint32_t Kj = K < J.k_limit ? K : J.k_limit;
+    const bool obs_only = (K == 0);
+    const uint32_t nsteps = obs_only ? 1u : Kj;
+
+    GAS uint32_t *obs_p = gp(J.obs) + ((uint64_t)J.out_step0 + step_base) * J.obs_stride + obs_off;
+    GAS float *rew_p = obs_only ? nullptr
+                                : gp(J.rew) + ((uint64_t)J.out_step0 + step_base) * J.agent_stride + agent_off;
+    GAS uint8_t *done_p = obs_only ? nullptr
+                                   : gp(J.done) + ((uint64_t)J.out_step0 + step_base) * J.env_stride + e;
+    const GAS int8_t *act_p =
+        J.act ? gp(J.act) + ((uint64_t)J.out_step0 + step_base) * J.agent_stride + agent_off : nullptr;
+
+    // Complete every load issued so far here, before the step loop: the wait
+    // pass would otherwise place a vmcnt(0) wait at their first use inside the
+    // loop, and on gfx9 vmcnt also counts stores, so each step would stall on
+    // all of the previous step's output stores.
+    __builtin_amdgcn_s_waitcnt(0);
+    wave_lds_fence();
+
+    uint64_t win = 0;  // generator blocks of the current action window
+    int j = 0;         // step within the current action window (runtime windows)
+    const bool has_act = J.act != nullptr;
+    // The step loop, instantiated for channels computed assuming distinct
+    // agent cells (collisions on) and for the exact per-agent test; the choice
+    // is made once per env, outside the loop.
+    auto run = [&](auto exact_tag) {
+        constexpr bool EX = decltype(exact_tag)::value;
+        uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W];
+        int cnt[TPL];
+        for (uint32_t k = 0; k < nsteps; ++k) {
+            if (!obs_only) {
+                // ---- 1 actions: 3 bits per agent
+                uint64_t acts = 0;
+                if constexpr (DPP_WINDOW) {
+                    const uint32_t jw = k & (uint32_t)(LANES - 1);
+                    if (jw == 0u) {
+                        const U4 x = philox(env, ST_ACTION << 24, steps + (uint32_t)l, 0u, k0, k1);
+                        const uint32_t mine_blk = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
+                                                  (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
+                        win = gather_window<LANES>(mine_blk);
+                    }
+                    acts = (win >> (12u * jw)) & 0xfffull;
+                } else if constexpr (WINDOWED) {
+                    if (j == 0) {
+                        const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)wgroup,
+                                            steps + (uint32_t)wstep, 0u, k0, k1);
+                        win = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
+                              (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
+                    }
+#pragma unroll
+                    for (int g = 0; g < MAXCALLS; ++g) {
+                        if (g < ncalls) {
+                            const uint32_t v =
+                                (uint32_t)__shfl((int)(uint32_t)win, q * LANES + j * ncalls + g, 64);
+                            acts |= (uint64_t)v << (12 * g);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int g = 0; g < MAXCALLS; ++g) {
+                        if (g < ncalls) {
+                            const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)g, steps, 0u, k0, k1);
+                            const uint32_t a4 = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
+                                                (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
+                            acts |= (uint64_t)a4 << (12 * g);
+                        }
+                    }
+                }
+                if (has_act) {
+                    uint64_t ov = 0, om = 0;
+#pragma unroll
+                    for (int i = 0; i < NMAX; ++i) {
+                        if (i < n) {
+                            const int v = act_p[i];
+                            if (v != -1) {
+                                const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                                ov |= (uint64_t)a << (3 * i);
+                                om |= 7ull << (3 * i);
+                            }
+                        }
+                    }
+                    acts = (acts & ~om) | ov;
+                    act_p += J.agent_stride;
+                }
+                acts &= amask;
+
+                // ---- 2 moves, agent-index order (redundant in every lane of the env)
+                int tgt[NMAX];
+                bool open[NMAX];
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
+                    const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
+                    tgt[i] = pp[i] + dl;
+                    uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)P + (((uint32_t)tgt[i] >> 5) & 7u);
+                    widx = widx < last_word ? widx : last_word;
+                    const uint32_t wbit = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
+                    open[i] = a != 0u && wbit == 0u;
+                }
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    bool clash = false;
+#pragma unroll
+                    for (int jj = 0; jj < NMAX; ++jj)
+                        if (jj != i) clash = clash || pp[jj] == tgt[i];
+                    pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
+                }
+                own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+
+                // ---- 3 detection (from the channels of the post-move positions)
+                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                                           wall, outm, team, opp, cnt);
+                uint32_t seen_h = 0;
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int a = l + m * LANES;
+                    const bool sa = a < S;
+                    if (active && a < n) rew_p[a] = (float)(sa ? cnt[m] : -cnt[m]);
+                    seen_h |= (a < n && !sa && cnt[m] > 0) ? (1u << a) : 0u;
+                }
+                found |= group_or_dpp<LANES>(seen_h);
+
+                // ---- 4 termination / truncation
+                t += 1u;
+                const bool term = (flags & 2u) && n > S && (found & hmask) == hmask;
+                const bool trunc = t >= Lep;
+                const uint32_t d = (term ? 1u : 0u) | (trunc ? 2u : 0u);
+                if (active && l == 0) *done_p = (uint8_t)d;
+
+                // ---- 5 same-step auto-reset from the unchanged grid
+                if (d) {
+                    ep += 1u;
+                    t = 0u;
+                    found = 0u;
+                    spawn_agents(spawned, n, H, Wd, slot, P, env, k0, k1, ep);
+                    wave_lds_fence();
+#pragma unroll
+                    for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
+                    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+                    all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S,
+                                               want_out, wall, outm, team, opp, cnt);
+                }
+
+                // ---- 6 generator step key
+                steps += 1u;
+                j = (j + 1 == kb) ? 0 : j + 1;
+                rew_p += J.agent_stride;
+                done_p += J.env_stride;
+            } else {
+                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                                           wall, outm, team, opp, cnt);
+            }
+
+            // ---- 7 observations of this lane's agents (channel-major words)
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                const int a = l + m * LANES;
+                if (active && a < n) {
+                    GAS uint32_t *oa = obs_p + (uint32_t)(a * C * W);
+                    store_words<W>(oa, wall[m]);
+                    store_words<W>(oa + W, team[m]);
+                    store_words<W>(oa + 2 * W, opp[m]);
+                    if (want_out) store_words<W>(oa + 3 * W, outm[m]);
+                }
+            }
+            obs_p += J.obs_stride;
+        }
+
+    };
+    if (collide)
+        run(std::false_type{});
+    else
+        run(std::true_type{});
+
+    // write back the state
+    if (active && !obs_only) {
+        if (l == 0) {
+            gp(J.found)[e] = found;
+            gp(J.t)[e] = t;
+            gp(J.ep)[e] = ep;
+            gp(J.steps)[e] = steps;
+        }
+#pragma unroll
+        for (int jj = 0; jj < NMAX; ++jj) {
+            if (jj < n && (jj % LANES) == l) {
+                const uint32_t x = (uint32_t)(pp[jj] & 0xff) - PAD, y = (uint32_t)(pp[jj] >> 8) - PAD;
+                gp(J.pos)[agent_off + (uint32_t)jj] = (uint16_t)(x | (y << 8));
+            }
+        }
+    }
+}
+
+// One variant: every tile of the launch has the same (LANES, NMAX, R).
+template <int LANES, int NMAX, int R>
+__global__ __launch_bounds__(64) void step_kernel(const Tile *__restrict__ tiles, uint32_t n_tiles,
+                                                  const JobDesc *__restrict__ jobs, JobDesc job0,
+                                                  uint32_t K, uint32_t step_base, uint32_t slot_words)
+{
+    extern __shared__ uint32_t lds[];
+    if (blockIdx.x >= n_tiles) return;
+    const Tile tile = tiles[blockIdx.x];
+    const JobDesc J = jobs ? jobs[tile.job] : job0;
+    step_tile<LANES, NMAX, R>(tile, J, K, step_base, slot_words, lds);
+}
+
+// Variant code of a tile: agent-count bucket * 4 + radius - 1.
+__host__ __device__ constexpr uint32_t variant_code(int bucket, int r) { return (uint32_t)(bucket * 4 + r - 1); }
+
+template <int LANES, int B>
+__device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobDesc &J, uint32_t K,
+                                             uint32_t step_base, uint32_t slot_words, uint32_t *lds)
+{
+    constexpr int NMAX = BUCKET_NMAX[B];
+    if constexpr ((NMAX + LANES - 1) / LANES <= 4) {
+        switch (r) {
+        case 1: step_tile<LANES, NMAX, 1>(tile, J, K, step_base, slot_words, lds); break;
+        case 2: step_tile<LANES, NMAX, 2>(tile, J, K, step_base, slot_words, lds); break;
+        case 3: step_tile<LANES, NMAX, 3>(tile, J, K, step_base, slot_words, lds); break;
+        default: step_tile<LANES, NMAX, 4>(tile, J, K, step_base, slot_words, lds); break;
+        }
+    }
+}
+
+// Mixed variants in one launch (uneven batches): each wave runs the code of
+// its own tile's (bucket, radius), chosen by a wave-uniform switch, so every
+// bucket of the batch shares the chip at once.
+template <int LANES>
+__global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__ tiles,
+                                                        uint32_t n_tiles,
+                                                        const JobDesc *__restrict__ jobs,
+                                                        JobDesc job0, uint32_t K,
+                                                        uint32_t step_base, uint32_t slot_words)
+{
+    extern __shared__ uint32_t lds[];
+    if (blockIdx.x >= n_tiles) return;
+    const Tile tile = tiles[blockIdx.x];
+    const JobDesc J = jobs ? jobs[tile.job] : job0;
+    const int bucket = (int)(tile.variant >> 2), r = (int)(tile.variant & 3u) + 1;
+    switch (bucket) {
+    case 0: mixed_bucket<LANES, 0>(r, tile, J, K, step_base, slot_words, lds); break;
+    case 1: mixed_bucket<LANES, 1>(r, tile, J, K, step_base, slot_words, lds); break;
+    case 2: mixed_bucket<LANES, 2>(r, tile, J, K, step_base, slot_words, lds); break;
+    default: mixed_bucket<LANES, 3>(r, tile, J, K, step_base, slot_words, lds); break;
+    }
+}
+
+// ------------------------------------------------------------ launch helpers
+
+template <int LANES, int NMAX, int R>
+inline hipError_t launch_variant(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
+                                 const JobDesc &job0, uint32_t K, uint32_t step_base,
+                                 uint32_t slot_words, hipStream_t stream)
+{
+    const size_t lds = (size_t)(64 / LANES) * (slot_words + MAX_AGENTS) * sizeof(uint32_t);
+    hipLaunchKernelGGL((step_kernel<LANES, NMAX, R>), dim3(n_tiles), dim3(64), lds, stream, tiles,
+                       n_tiles, jobs, job0, K, step_base, slot_words);
+    return hipGetLastError();
+}
+
+template <int LANES, int NMAX>
+inline hipError_t launch_radius(int r, const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
+                                const JobDesc &job0, uint32_t K, uint32_t step_base,
+                                uint32_t slot_words, hipStream_t stream)
+{
+    if constexpr ((NMAX + LANES - 1) / LANES > 4) {
+        return hipErrorInvalidValue;
+    } else {
+    switch (r) {
+    case 1: return launch_variant<LANES, NMAX, 1>(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    case 2: return launch_variant<LANES, NMAX, 2>(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    case 3: return launch_variant<LANES, NMAX, 3>(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    case 4: return launch_variant<LANES, NMAX, 4>(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    default: return hipErrorInvalidValue;
+    }
+    }
+}
+
+template <int LANES>
+inline hipError_t launch_lanes(int nmax, int r, const Tile *tiles, uint32_t n_tiles,
+                               const JobDesc *jobs, const JobDesc &job0, uint32_t K,
+                               uint32_t step_base, uint32_t slot_words, hipStream_t stream)
+{
+    switch (nmax) {
+    case 2: return launch_radius<LANES, 2>(r, tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    case 4: return launch_radius<LANES, 4>(r, tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    case 10: return launch_radius<LANES, 10>(r, tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    case 20: return launch_radius<LANES, 20>(r, tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LANES>
+inline hipError_t launch_mixed_l(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
+                                 const JobDesc &job0, uint32_t K, uint32_t step_base,
+                                 uint32_t slot_words, hipStream_t stream)
+{
+    const size_t lds = (size_t)(64 / LANES) * (slot_words + MAX_AGENTS) * sizeof(uint32_t);
+    hipLaunchKernelGGL((step_kernel_mixed<LANES>), dim3(n_tiles), dim3(64), lds, stream, tiles,
+                       n_tiles, jobs, job0, K, step_base, slot_words);
+    return hipGetLastError();
+}
+
+}  // namespace hase

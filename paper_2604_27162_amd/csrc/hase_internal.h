@@ -57,9 +57,11 @@ struct JobDesc {
     uint32_t out_step0;   // output step index of the job's first step in this launch
 };
 
-// A wave's work: envs perm[env0 .. env0 + count) of job `job` (count <= 64 / lanes).
+// A wave's work: envs perm[env0 .. env0 + count) of job `job` (count <= 64 /
+// lanes); variant = agent-count bucket * 4 + view radius - 1 (read by the
+// mixed-variant kernel).
 struct Tile {
-    uint32_t job, env0, count, pad;
+    uint32_t job, env0, count, variant;
 };
 
 struct InitArgs {
@@ -82,7 +84,28 @@ hipError_t launch_step(int lanes, int nmax, int r, const Tile *tiles, uint32_t n
                        const JobDesc *jobs, const JobDesc &job0, uint32_t K,
                        uint32_t step_base, uint32_t slot_words, hipStream_t stream);
 
+// One launch over tiles of several (bucket, radius) variants that share
+// `lanes`; slot_words is the largest board among them.
+hipError_t launch_mixed(int lanes, const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
+                        const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
+                        hipStream_t stream);
+
 hipError_t launch_init(const InitArgs &a, hipStream_t stream);
+
+// Per-lanes entry points, one translation unit each (hase_step_l<L>.hip).
+#define HASE_DECLARE_LANES(L)                                                                     \
+    hipError_t launch_step_lanes##L(int nmax, int r, const Tile *tiles, uint32_t n_tiles,        \
+                                    const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
+                                    uint32_t step_base, uint32_t slot_words, hipStream_t stream); \
+    hipError_t launch_mixed_lanes##L(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,   \
+                                     const JobDesc &job0, uint32_t K, uint32_t step_base,         \
+                                     uint32_t slot_words, hipStream_t stream);
+HASE_DECLARE_LANES(1)
+HASE_DECLARE_LANES(2)
+HASE_DECLARE_LANES(4)
+HASE_DECLARE_LANES(8)
+HASE_DECLARE_LANES(16)
+#undef HASE_DECLARE_LANES
 
 bool variant_supported(int lanes, int nmax);
 

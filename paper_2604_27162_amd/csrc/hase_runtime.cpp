@@ -164,8 +164,11 @@ int make_plan(const hase_batch_desc *d, Plan &p)
     return HASE_OK;
 }
 
+// One kernel launch of a step call: a single (bucket, radius) variant, or
+// (mixed) every variant sharing `lanes`, over contiguous tiles.
 struct Variant {
     int lanes = 0, nmax = 0, r = 0;
+    bool mixed = false;
     uint32_t tile0 = 0, n_tiles = 0, slot_words = 0;
 };
 
@@ -219,7 +222,8 @@ void drop_graphs(hase_batch *b)
 
 // Group envs by (agent-count bucket, view radius) -- one kernel variant each --,
 // order each group by (n, area) so a wave holds similar envs, and cut it into
-// tiles of 64 / lanes envs.
+// tiles of 64 / lanes envs. Variants that share a lanes-per-env value run as
+// one mixed launch, so all buckets of an uneven batch share the chip.
 int build_tiles(hase_batch *b)
 {
     const Plan &p = b->plan;
@@ -228,44 +232,53 @@ int build_tiles(hase_batch *b)
     perm.reserve(N);
     std::vector<Tile> tiles;
     std::vector<Variant> vars;
-    for (int bk = 0; bk < N_BUCKETS; ++bk) {
-        for (int r = 1; r <= PAD; ++r) {
-            std::vector<uint32_t> ids;
-            for (uint32_t e = 0; e < N; ++e)
-                if (bucket_of(p.specs[e].n_agents) == bk && p.specs[e].view_radius == r) ids.push_back(e);
-            if (ids.empty()) continue;
-            std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
-                const hase_env_spec &x = p.specs[a], &y = p.specs[c];
-                if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
-                return x.height * x.width > y.height * y.width;
-            });
-            Variant v;
-            v.lanes = (int)b->lanes[bk];
-            v.nmax = BUCKET_NMAX[bk];
-            v.r = r;
-            v.tile0 = (uint32_t)tiles.size();
-            const uint32_t E = 64u / (uint32_t)v.lanes;
-            const uint32_t base = (uint32_t)perm.size();
-            uint32_t slot = 0;
-            for (uint32_t e : ids) {
-                perm.push_back(e);
-                slot = std::max(slot, (uint32_t)board_words(p.specs[e].height, p.specs[e].width));
+    const uint32_t lane_order[] = {1, 2, 4, 8, 16};
+    for (uint32_t L : lane_order) {
+        Variant grp;
+        grp.lanes = (int)L;
+        grp.tile0 = (uint32_t)tiles.size();
+        int n_var = 0;
+        for (int bk = 0; bk < N_BUCKETS; ++bk) {
+            if (b->lanes[bk] != L) continue;
+            for (int r = 1; r <= PAD; ++r) {
+                std::vector<uint32_t> ids;
+                for (uint32_t e = 0; e < N; ++e)
+                    if (bucket_of(p.specs[e].n_agents) == bk && p.specs[e].view_radius == r)
+                        ids.push_back(e);
+                if (ids.empty()) continue;
+                std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
+                    const hase_env_spec &x = p.specs[a], &y = p.specs[c];
+                    if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
+                    return x.height * x.width > y.height * y.width;
+                });
+                const uint32_t E = 64u / L;
+                const uint32_t base = (uint32_t)perm.size();
+                for (uint32_t e : ids) {
+                    perm.push_back(e);
+                    grp.slot_words = std::max(grp.slot_words,
+                                              (uint32_t)board_words(p.specs[e].height, p.specs[e].width));
+                }
+                for (uint32_t i = 0; i < ids.size(); i += E) {
+                    Tile t;
+                    t.job = 0;
+                    t.env0 = base + i;
+                    t.count = std::min<uint32_t>(E, (uint32_t)ids.size() - i);
+                    t.variant = (uint32_t)(bk * 4 + r - 1);
+                    tiles.push_back(t);
+                }
+                grp.nmax = BUCKET_NMAX[bk];
+                grp.r = r;
+                ++n_var;
             }
-            for (uint32_t i = 0; i < ids.size(); i += E) {
-                Tile t;
-                t.job = 0;
-                t.env0 = base + i;
-                t.count = std::min<uint32_t>(E, (uint32_t)ids.size() - i);
-                t.pad = 0;
-                tiles.push_back(t);
-            }
-            v.n_tiles = (uint32_t)tiles.size() - v.tile0;
-            v.slot_words = slot;
-            if ((size_t)E * slot * 4 > 65536)
-                return fail(HASE_EINVAL, "tiling: %u lanes/env needs %zu bytes of LDS per wave",
-                            v.lanes, (size_t)E * slot * 4);
-            vars.push_back(v);
         }
+        if (n_var == 0) continue;
+        grp.mixed = n_var > 1;
+        grp.n_tiles = (uint32_t)tiles.size() - grp.tile0;
+        const size_t lds_bytes = (size_t)(64u / L) * (grp.slot_words + MAX_AGENTS) * 4;
+        if (lds_bytes > 65536)
+            return fail(HASE_EINVAL, "tiling: %u lanes/env needs %zu bytes of LDS per wave", L,
+                        lds_bytes);
+        vars.push_back(grp);
     }
     if (tiles.size() > p.max_tiles) return fail(HASE_EINVAL, "tile table overflow");
     HIP_TRY(hipMemcpyAsync(b->d + p.reg.perm, perm.data(), 4 * perm.size(), hipMemcpyHostToDevice,
@@ -316,8 +329,12 @@ int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, h
             HIP_TRY(hipStreamWaitEvent(b->side[i], b->fork_ev, 0));
             s = b->side[i];
         }
-        HIP_TRY(launch_step(v.lanes, v.nmax, v.r, tiles + v.tile0, v.n_tiles, nullptr, job, K,
-                            step_base, v.slot_words, s));
+        if (v.mixed)
+            HIP_TRY(launch_mixed(v.lanes, tiles + v.tile0, v.n_tiles, nullptr, job, K, step_base,
+                                 v.slot_words, s));
+        else
+            HIP_TRY(launch_step(v.lanes, v.nmax, v.r, tiles + v.tile0, v.n_tiles, nullptr, job, K,
+                                step_base, v.slot_words, s));
         if (fork && i > 0) {
             HIP_TRY(hipEventRecord(b->join_ev[i], s));
             HIP_TRY(hipStreamWaitEvent(stream, b->join_ev[i], 0));

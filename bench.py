@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="single16k", choices=sorted(DESCR))
     ap.add_argument("--lanes", default=None, help="lanes per env per agent bucket, e.g. 4,4,16,16")
+    ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
+                    help="choose the tiling with the autotuner (timed runs of STEPS steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-launch", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -154,6 +156,8 @@ def main():
     g = hase.HaseBatch(specs, device="cuda:0", lanes=lanes)
     stream = g.stream
     g.reset(w["seed"])
+    if args.autotune:
+        lanes = g.autotune(args.autotune)
     obs, rew, done = g.alloc_outputs(K)
     if W > 0:
         g.step_into(obs, rew, done, W)

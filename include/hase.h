@@ -202,6 +202,42 @@ int hase_set_state(hase_batch *b, const hase_host_state *in);
 int hase_set_tiling(hase_batch *b, const uint32_t lanes[HASE_N_BUCKETS]);
 int hase_get_tiling(const hase_batch *b, uint32_t lanes[HASE_N_BUCKETS]);
 
+/*
+ * Autotuner of the tiling: coordinate descent over lanes_per_env of every
+ * agent-count bucket present in the batch, timing persistent calls of
+ * n_steps (HIP events on the handle's stream) into the caller's scratch
+ * outputs (sized as for hase_step with n_steps). The state is snapshotted
+ * and restored, so tuning does not advance the envs, and results never depend
+ * on the tiling. Applies the fastest tiling found and copies it to lanes_out
+ * (may be NULL). Synchronises the stream.
+ */
+int hase_autotune(hase_batch *b, uint32_t n_steps, uint32_t *d_obs, float *d_rew, uint8_t *d_done,
+                  uint32_t lanes_out[HASE_N_BUCKETS]);
+
+/*
+ * Serving: several batches (one per request, each with its own state) stepped
+ * together, one launch per lanes-per-env value across all of them. Request i
+ * takes io[i].n_steps <= n_steps steps; its outputs (and optional actions)
+ * are indexed by output step io[i].out_step0 + k in its own buffers, laid out
+ * as for hase_step. Handles must be distinct and not in use elsewhere; the
+ * work is enqueued on `stream` (a hipStream_t). d_workspace is caller device
+ * memory of hase_multi_workspace bytes (job and tile tables), which must stay
+ * untouched until the launch completes.
+ */
+typedef struct hase_step_io {
+    hase_batch *batch;
+    uint32_t n_steps;
+    uint32_t out_step0;
+    const int8_t *d_actions;
+    uint32_t *d_obs;
+    float *d_rew;
+    uint8_t *d_done;
+} hase_step_io;
+
+int hase_multi_workspace(hase_batch *const *batches, uint32_t n, uint64_t *bytes);
+int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *d_workspace,
+                    uint64_t workspace_bytes, void *stream);
+
 /* Release the handle (never frees caller memory). */
 int hase_destroy(hase_batch *b);
 

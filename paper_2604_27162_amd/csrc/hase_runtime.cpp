@@ -188,6 +188,7 @@ struct hase_batch {
     bool ready = false;
     uint32_t lanes[N_BUCKETS];
     std::vector<Variant> variants;
+    std::vector<Tile> host_tiles;  // host copy of the device tile table
     hipStream_t side[MAX_VARIANTS] = {};
     hipEvent_t fork_ev = nullptr, join_ev[MAX_VARIANTS] = {};
     std::list<GraphEntry> graphs;  // most recently used first
@@ -287,6 +288,7 @@ int build_tiles(hase_batch *b)
                            hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->variants = vars;
+    b->host_tiles = tiles;
     drop_graphs(b);
     return HASE_OK;
 }
@@ -429,6 +431,80 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
     a.n_envs = b->n_envs;
     a.rebuild_only = rebuild;
     return a;
+}
+
+// Mutable per-env state (walls and bitboards never change while stepping).
+struct Snapshot {
+    std::vector<uint16_t> pos;
+    std::vector<uint32_t> found, t, ep, steps;
+};
+
+int snapshot_take(hase_batch *b, Snapshot &s)
+{
+    const Plan &p = b->plan;
+    const uint32_t N = b->n_envs;
+    s.pos.resize(p.agents);
+    s.found.resize(N);
+    s.t.resize(N);
+    s.ep.resize(N);
+    s.steps.resize(N);
+    auto down = [&](void *dst, size_t off, size_t bytes) {
+        return hipMemcpyAsync(dst, b->d + off, bytes, hipMemcpyDeviceToHost, b->stream);
+    };
+    HIP_TRY(down(s.pos.data(), p.reg.pos, 2 * p.agents));
+    HIP_TRY(down(s.found.data(), p.reg.found, 4ull * N));
+    HIP_TRY(down(s.t.data(), p.reg.t, 4ull * N));
+    HIP_TRY(down(s.ep.data(), p.reg.ep, 4ull * N));
+    HIP_TRY(down(s.steps.data(), p.reg.steps, 4ull * N));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return HASE_OK;
+}
+
+int snapshot_restore(hase_batch *b, const Snapshot &s)
+{
+    const Plan &p = b->plan;
+    const uint32_t N = b->n_envs;
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        return hipMemcpyAsync(b->d + off, src, bytes, hipMemcpyHostToDevice, b->stream);
+    };
+    HIP_TRY(up(p.reg.pos, s.pos.data(), 2 * p.agents));
+    HIP_TRY(up(p.reg.found, s.found.data(), 4ull * N));
+    HIP_TRY(up(p.reg.t, s.t.data(), 4ull * N));
+    HIP_TRY(up(p.reg.ep, s.ep.data(), 4ull * N));
+    HIP_TRY(up(p.reg.steps, s.steps.data(), 4ull * N));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return HASE_OK;
+}
+
+// Milliseconds of a persistent call of n_steps under the current tiling: the
+// faster of two timed calls, after an untimed one that also captures the
+// graph; the state is restored before each call and at the end.
+int time_tiling(hase_batch *b, const JobDesc &job, uint32_t n_steps, const Snapshot &snap,
+                float *ms)
+{
+    int rc = persistent_step(b, job, n_steps);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t err = hipSuccess;
+    *ms = 0.f;
+    for (int rep = 0; rep < 2 && !rc && err == hipSuccess; ++rep) {
+        rc = snapshot_restore(b, snap);
+        if (rc) break;
+        err = hipEventRecord(e0, b->stream);
+        if (err == hipSuccess) rc = persistent_step(b, job, n_steps);
+        if (err == hipSuccess && !rc) err = hipEventRecord(e1, b->stream);
+        if (err == hipSuccess && !rc) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess && !rc) err = hipEventElapsedTime(&t, e0, e1);
+        if (err == hipSuccess && !rc) *ms = rep == 0 ? t : std::min(*ms, t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (err != hipSuccess) return hip_fail(err, "autotune timing");
+    return snapshot_restore(b, snap);
 }
 
 }  // namespace
@@ -665,6 +741,141 @@ int hase_get_tiling(const hase_batch *b, uint32_t lanes[HASE_N_BUCKETS])
 {
     if (!b || !lanes) return fail(HASE_EINVAL, "null argument");
     for (int i = 0; i < N_BUCKETS; ++i) lanes[i] = b->lanes[i];
+    return HASE_OK;
+}
+
+int hase_autotune(hase_batch *b, uint32_t n_steps, uint32_t *d_obs, float *d_rew, uint8_t *d_done,
+                  uint32_t lanes_out[HASE_N_BUCKETS])
+{
+    const int rc0 = check_step_args(b, n_steps, d_obs, d_rew, d_done);
+    if (rc0) return rc0;
+    Snapshot snap;
+    int rc = snapshot_take(b, snap);
+    if (rc) return rc;
+    bool present[N_BUCKETS] = {};
+    for (const hase_env_spec &s : b->plan.specs) present[bucket_of(s.n_agents)] = true;
+    const JobDesc job = make_job(b, nullptr, d_obs, d_rew, d_done);
+    uint32_t best[N_BUCKETS];
+    std::memcpy(best, b->lanes, sizeof best);
+    float best_ms = 0.f;
+    rc = time_tiling(b, job, n_steps, snap, &best_ms);
+    if (rc) return rc;
+    const uint32_t cands[] = {1, 2, 4, 8, 16};
+    for (int bk = 0; bk < N_BUCKETS; ++bk) {
+        if (!present[bk]) continue;
+        for (uint32_t L : cands) {
+            if (L == best[bk] || !variant_supported((int)L, BUCKET_NMAX[bk])) continue;
+            std::memcpy(b->lanes, best, sizeof best);
+            b->lanes[bk] = L;
+            if (build_tiles(b) != HASE_OK) continue;  // e.g. LDS too small for this shape
+            float ms = 0.f;
+            rc = time_tiling(b, job, n_steps, snap, &ms);
+            if (rc) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best[bk] = L;
+            }
+        }
+        if (rc) break;
+    }
+    std::memcpy(b->lanes, best, sizeof best);
+    const int rc2 = build_tiles(b);
+    const int rc3 = snapshot_restore(b, snap);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (rc3) return rc3;
+    if (lanes_out)
+        for (int i = 0; i < N_BUCKETS; ++i) lanes_out[i] = best[i];
+    return HASE_OK;
+}
+
+int hase_multi_workspace(hase_batch *const *batches, uint32_t n, uint64_t *bytes)
+{
+    if (!bytes || (n && !batches)) return fail(HASE_EINVAL, "null argument");
+    size_t tiles = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!batches[i]) return fail(HASE_EINVAL, "null handle %u", i);
+        tiles += batches[i]->host_tiles.size();
+    }
+    *bytes = align256(sizeof(JobDesc) * (size_t)(n ? n : 1)) + align256(sizeof(Tile) * (tiles ? tiles : 1));
+    return HASE_OK;
+}
+
+int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *d_workspace,
+                    uint64_t workspace_bytes, void *stream)
+{
+    if (n == 0) return HASE_OK;
+    if (!io || !d_workspace) return fail(HASE_EINVAL, "null argument");
+    if (n_steps == 0) return fail(HASE_EINVAL, "n_steps must be >= 1");
+    std::vector<hase_batch *> bs(n);
+    std::vector<JobDesc> jobs(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        hase_batch *b = io[i].batch;
+        const int rc = check_step_args(b, io[i].n_steps, io[i].d_obs, io[i].d_rew, io[i].d_done);
+        if (rc) return fail(rc, "request %u: %s", i, g_last_error.c_str());
+        if (io[i].n_steps > n_steps)
+            return fail(HASE_EINVAL, "request %u: %u steps > call's %u", i, io[i].n_steps, n_steps);
+        for (uint32_t j = 0; j < i; ++j)
+            if (bs[j] == b) return fail(HASE_EINVAL, "request %u repeats a batch handle", i);
+        bs[i] = b;
+        jobs[i] = make_job(b, io[i].d_actions, io[i].d_obs, io[i].d_rew, io[i].d_done);
+        jobs[i].k_limit = io[i].n_steps;
+        jobs[i].out_step0 = io[i].out_step0;
+    }
+    uint64_t need = 0;
+    int rc = hase_multi_workspace(bs.data(), n, &need);
+    if (rc) return rc;
+    if (workspace_bytes < need)
+        return fail(HASE_ENOMEM, "workspace has %llu bytes, needs %llu",
+                    (unsigned long long)workspace_bytes, (unsigned long long)need);
+    // one launch group per lanes value across all requests; a group whose
+    // tiles carry more than one variant code runs the mixed kernel
+    struct Group {
+        uint32_t lanes = 0, tile0 = 0, n_tiles = 0, slot = 0, code0 = 0;
+        bool mixed = false;
+    };
+    std::vector<Tile> tiles;
+    std::vector<Group> groups;
+    const uint32_t lane_order[] = {1, 2, 4, 8, 16};
+    for (uint32_t L : lane_order) {
+        Group g;
+        g.lanes = L;
+        g.tile0 = (uint32_t)tiles.size();
+        for (uint32_t i = 0; i < n; ++i) {
+            for (const Variant &v : bs[i]->variants) {
+                if ((uint32_t)v.lanes != L) continue;
+                for (uint32_t t = v.tile0; t < v.tile0 + v.n_tiles; ++t) {
+                    Tile tl = bs[i]->host_tiles[t];
+                    tl.job = i;
+                    if (tiles.size() == g.tile0)
+                        g.code0 = tl.variant;
+                    else if (tl.variant != g.code0)
+                        g.mixed = true;
+                    tiles.push_back(tl);
+                }
+                g.slot = std::max(g.slot, v.slot_words);
+            }
+        }
+        g.n_tiles = (uint32_t)tiles.size() - g.tile0;
+        if (g.n_tiles) groups.push_back(g);
+    }
+    char *ws = static_cast<char *>(d_workspace);
+    const size_t jobs_bytes = align256(sizeof(JobDesc) * n);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(ws, jobs.data(), sizeof(JobDesc) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ws + jobs_bytes, tiles.data(), sizeof(Tile) * tiles.size(),
+                           hipMemcpyHostToDevice, st));
+    const JobDesc *djobs = reinterpret_cast<const JobDesc *>(ws);
+    const Tile *dtiles = reinterpret_cast<const Tile *>(ws + jobs_bytes);
+    for (const Group &g : groups) {
+        if (g.mixed)
+            HIP_TRY(launch_mixed((int)g.lanes, dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps,
+                                 0, g.slot, st));
+        else
+            HIP_TRY(launch_step((int)g.lanes, BUCKET_NMAX[g.code0 >> 2], (int)(g.code0 & 3u) + 1,
+                                dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps, 0, g.slot,
+                                st));
+    }
     return HASE_OK;
 }
 

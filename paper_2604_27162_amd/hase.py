@@ -56,9 +56,16 @@ class HostState(ctypes.Structure):
                 ("seed", ctypes.c_void_p)]
 
 
+class StepIO(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_void_p), ("n_steps", ctypes.c_uint32),
+                ("out_step0", ctypes.c_uint32), ("d_actions", ctypes.c_void_p),
+                ("d_obs", ctypes.c_void_p), ("d_rew", ctypes.c_void_p), ("d_done", ctypes.c_void_p)]
+
+
 EXPORTS = ("hase_query_layout", "hase_create", "hase_get_offsets", "hase_reset", "hase_step",
            "hase_prepare", "hase_observe", "hase_get_state", "hase_set_state", "hase_set_tiling",
-           "hase_get_tiling", "hase_destroy", "hase_strerror", "hase_last_error")
+           "hase_get_tiling", "hase_autotune", "hase_multi_workspace", "hase_step_multi",
+           "hase_destroy", "hase_strerror", "hase_last_error")
 
 _lib = None
 
@@ -84,6 +91,9 @@ def load(path: str = LIB_PATH):
         "hase_set_state": [vp, ctypes.POINTER(HostState)],
         "hase_set_tiling": [vp, ctypes.POINTER(u32 * N_BUCKETS)],
         "hase_get_tiling": [vp, ctypes.POINTER(u32 * N_BUCKETS)],
+        "hase_autotune": [vp, u32, vp, vp, vp, ctypes.POINTER(u32 * N_BUCKETS)],
+        "hase_multi_workspace": [ctypes.POINTER(vp), u32, ctypes.POINTER(u64)],
+        "hase_step_multi": [ctypes.POINTER(StepIO), u32, u32, vp, u64, vp],
         "hase_destroy": [vp],
         "hase_strerror": [ctypes.c_int],
         "hase_last_error": [],
@@ -244,6 +254,19 @@ class HaseBatch:
         _check(load().hase_get_tiling(self._h, ctypes.byref(arr)))
         return list(arr)
 
+    def autotune(self, n_steps: int = 256):
+        """Choose lanes-per-env per agent bucket by timing short persistent runs
+        (the state is restored afterwards); returns the chosen tiling."""
+        obs, rew, done = self.alloc_outputs(n_steps)
+        arr = (ctypes.c_uint32 * N_BUCKETS)()
+        _check(load().hase_autotune(self._h, int(n_steps), obs.data_ptr(), rew.data_ptr(),
+                                    done.data_ptr(), ctypes.byref(arr)))
+        return list(arr)
+
+    @property
+    def handle(self):
+        return self._h
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             load().hase_destroy(self._h)
@@ -259,3 +282,22 @@ class HaseBatch:
 def as_u32(t) -> np.ndarray:
     """Host uint32 view of an int32 obs tensor."""
     return t.detach().cpu().numpy().view(np.uint32)
+
+
+def multi_workspace_bytes(batches) -> int:
+    arr = (ctypes.c_void_p * max(1, len(batches)))(*[b.handle.value for b in batches])
+    out = ctypes.c_uint64()
+    _check(load().hase_multi_workspace(arr, len(batches), ctypes.byref(out)))
+    return int(out.value)
+
+
+def step_multi(items, n_steps: int, workspace, stream) -> None:
+    """Enqueue one multi-batch step: items are (batch, steps, out_step0,
+    actions or None, obs, rew, done) with per-batch device tensors."""
+    ios = (StepIO * max(1, len(items)))()
+    for i, (b, k, s0, act, obs, rew, done) in enumerate(items):
+        ios[i] = StepIO(b.handle.value, int(k), int(s0), None if act is None else act.data_ptr(),
+                        obs.data_ptr(), rew.data_ptr(), done.data_ptr())
+    _check(load().hase_step_multi(ios, len(items), int(n_steps), workspace.data_ptr(),
+                                  workspace.numel() * workspace.element_size(),
+                                  ctypes.c_void_p(stream.cuda_stream)))

@@ -162,7 +162,8 @@ __device__ __forceinline__ void window_rows(const uint32_t *slot, int P, int H, 
     constexpr int D = 2 * R + 1;
     constexpr uint32_t DM = (1u << D) - 1u;
     const int col = ax - R;  // padded column of the window's left edge
-    const uint32_t *base = slot + (ay - R) * P + (col >> 5);
+    // ay - R >= PAD - R >= 0: a 24-bit multiply suffices
+    const uint32_t *base = slot + __umul24((uint32_t)(ay - R), (uint32_t)P) + (col >> 5);
     const uint32_t sh = (uint32_t)(col & 31);
 #pragma unroll
     for (int rho = 0; rho < D; ++rho) {
@@ -277,14 +278,16 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, i
     window_rows<R, W>(slot, P, H, Wd, ax, ay, want_out, wall, outm);
     const bool sa = a < S;
     if constexpr (!EXACT) {
-        // bits of all agents in the window, and of the seekers among them
+        // bits of all agents in the window, and of the seekers among them;
+        // one select per bit (a 64-bit shift), so no scalar mask logic
         uint64_t all_lo = 0, sk_lo = 0;
         uint32_t all_hi = 0, sk_hi = 0;  // window bits 64.. (radius 4 only)
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) {
             const uint32_t dx = (uint32_t)((pp[j] & 0xff) - ax + R);
             const uint32_t dy = (uint32_t)((pp[j] >> 8) - ay + R);
-            const uint32_t kk = dy * (uint32_t)D + dx;
+            // only used when the agent is in the window (dx, dy < D)
+            const uint32_t kk = (uint32_t)__umul24(dy, (uint32_t)D) + dx;
             const uint32_t m = dx > dy ? dx : dy;
             const bool in = m < (uint32_t)D;
             const bool js = j < S;
@@ -326,7 +329,7 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, i
             const int dx = (pp[j] & 0xff) - ax + R;
             const int dy = (pp[j] >> 8) - ay + R;
             const bool in = j < n && j != a && (uint32_t)dx < (uint32_t)D && (uint32_t)dy < (uint32_t)D;
-            const int kk = dy * D + dx;
+            const int kk = __umul24((uint32_t)dy, (uint32_t)D) + dx;
             const uint32_t bit = in ? (1u << (kk & 31)) : 0u;
             const bool same = (j < S) == sa;
             cnt += (in && !same) ? 1 : 0;
@@ -355,10 +358,48 @@ __device__ __forceinline__ void all_masks(const uint32_t *slot, int P, int H, in
                                                 want_out, wall[m], outm[m], team[m], opp[m]);
 }
 
+// Blocked-move field of one agent, 5 bits: bit 0 set (action 0, stay, never
+// moves), bits 1..4 = the target cells of actions 1..4 (north, south, east,
+// west) hold a wall or lie outside the map. From the agent's wall|outside
+// window around its current cell, or from the board at cell pa.
+template <int R, int W>
+__device__ __forceinline__ uint32_t blocked_field(const uint32_t (&wall)[W])
+{
+    constexpr int D = 2 * R + 1, C = R * D + R;
+    auto bit = [&](int k) { return (wall[k >> 5] >> (k & 31)) & 1u; };
+    return 1u | (bit(C - D) << 1) | (bit(C + D) << 2) | (bit(C + 1) << 3) | (bit(C - 1) << 4);
+}
+
+__device__ __forceinline__ uint32_t blocked_field_board(const uint32_t *slot, int P, int pa)
+{
+    return 1u | (board_bit(slot, P, pa - 256) << 1) | (board_bit(slot, P, pa + 256) << 2) |
+           (board_bit(slot, P, pa + 1) << 3) | (board_bit(slot, P, pa - 1) << 4);
+}
+
+// Fields of agents 0..NMAX-1 (NMAX <= 6) at bits 5a.., gathered from the
+// lanes that own them: every lane of the env gets the same word.
+template <int LANES, int NMAX, int TPL, typename F>
+__device__ __forceinline__ uint32_t gather_blocked(int l, F field)
+{
+    static_assert(NMAX * 5 <= 32, "blocked fields need NMAX <= 6");
+    // when every task slot fits the word, slots of absent agents (whose
+    // actions are always 0) need no test
+    constexpr bool ALL_FIT = LANES * TPL * 5 <= 32;
+    uint32_t v = 0;
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+        const int a = l + m * LANES;
+        v |= (ALL_FIT || a < NMAX) ? field(m) << (5 * a) : 0u;
+    }
+    return group_or_dpp<LANES>(v);
+}
+
 // K steps of one tile: the envs perm[tile.env0 ..] of job J, LANES lanes per
 // env, at most NMAX agents, view radius R. K == 0 writes the observation of
-// the current state only.
-template <int LANES, int NMAX, int R>
+// the current state only. UNROLL unrolls the step loop over each action
+// window (single-variant launches; the mixed kernel keeps one copy per
+// variant to bound its code size).
+template <int LANES, int NMAX, int R, bool UNROLL>
 __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, uint32_t K,
                                           uint32_t step_base, uint32_t slot_words, uint32_t *lds)
 {
@@ -372,6 +413,9 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // with at most 4 agents and 2 or 4 lanes the window is gathered by DPP and
     // spans exactly LANES steps
     constexpr bool DPP_WINDOW = WINDOWED && NMAX <= 4 && (LANES == 2 || LANES == 4);
+    // with at most 4 agents the wall tests of the moves come from bits kept
+    // from the previous step's windows instead of board reads
+    constexpr bool NBR = NMAX <= 4;
 
     const int lane = (int)threadIdx.x;
     const int q = lane / LANES;  // env slot in the tile
@@ -447,9 +491,28 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     __builtin_amdgcn_s_waitcnt(0);
     wave_lds_fence();
 
-    uint64_t win = 0;  // generator blocks of the current action window
-    int j = 0;         // step within the current action window (runtime windows)
+    // blocked-move fields of all agents at their current cells (NBR only)
+    uint32_t nbw = 0;
+    if constexpr (NBR)
+        nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field_board(slot, P, mine[m]); });
+
     const bool has_act = J.act != nullptr;
+    // per-task constants: the task's agent exists (and its env is active), its
+    // bit in the hider mask, its reward sign
+    bool mine_live[TPL];
+    uint32_t hbit[TPL];
+    int rsign[TPL];
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+        const int a = l + m * LANES;
+        mine_live[m] = active && a < n;
+        hbit[m] = (a < n && a >= S) ? 1u << a : 0u;
+        rsign[m] = a < S ? 1 : -1;
+    }
+    // termination needs every hider found; without capture-ends (or without
+    // hiders) the test uses bit 31, which no agent sets
+    const uint32_t tmask = ((flags & 2u) && n > S) ? hmask : 0x80000000u;
+
     // The step loop, instantiated for channels computed assuming distinct
     // agent cells (collisions on) and for the exact per-agent test; the choice
     // is made once per env, outside the loop.
@@ -457,145 +520,176 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         constexpr bool EX = decltype(exact_tag)::value;
         uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W];
         int cnt[TPL];
-        for (uint32_t k = 0; k < nsteps; ++k) {
-            if (!obs_only) {
-                // ---- 1 actions: 3 bits per agent
-                uint64_t acts = 0;
-                if constexpr (DPP_WINDOW) {
-                    const uint32_t jw = k & (uint32_t)(LANES - 1);
-                    if (jw == 0u) {
-                        const U4 x = philox(env, ST_ACTION << 24, steps + (uint32_t)l, 0u, k0, k1);
-                        const uint32_t mine_blk = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
-                                                  (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
-                        win = gather_window<LANES>(mine_blk);
-                    }
-                    acts = (win >> (12u * jw)) & 0xfffull;
-                } else if constexpr (WINDOWED) {
-                    if (j == 0) {
-                        const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)wgroup,
-                                            steps + (uint32_t)wstep, 0u, k0, k1);
-                        win = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
-                              (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
-                    }
-#pragma unroll
-                    for (int g = 0; g < MAXCALLS; ++g) {
-                        if (g < ncalls) {
-                            const uint32_t v =
-                                (uint32_t)__shfl((int)(uint32_t)win, q * LANES + j * ncalls + g, 64);
-                            acts |= (uint64_t)v << (12 * g);
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int g = 0; g < MAXCALLS; ++g) {
-                        if (g < ncalls) {
-                            const U4 x = philox(env, (ST_ACTION << 24) | (uint32_t)g, steps, 0u, k0, k1);
-                            const uint32_t a4 = range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) |
-                                                (range_map(x.z, 5u) << 6) | (range_map(x.w, 5u) << 9);
-                            acts |= (uint64_t)a4 << (12 * g);
-                        }
-                    }
-                }
-                if (has_act) {
-                    uint64_t ov = 0, om = 0;
-#pragma unroll
-                    for (int i = 0; i < NMAX; ++i) {
-                        if (i < n) {
-                            const int v = act_p[i];
-                            if (v != -1) {
-                                const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
-                                ov |= (uint64_t)a << (3 * i);
-                                om |= 7ull << (3 * i);
-                            }
-                        }
-                    }
-                    acts = (acts & ~om) | ov;
-                    act_p += J.agent_stride;
-                }
-                acts &= amask;
 
-                // ---- 2 moves, agent-index order (redundant in every lane of the env)
-                int tgt[NMAX];
-                bool open[NMAX];
+        auto store_obs = [&](int m) __attribute__((always_inline)) {
+            GAS uint32_t *oa = obs_p + (uint32_t)((l + m * LANES) * C * W);
+            store_words<W>(oa, wall[m]);
+            store_words<W>(oa + W, team[m]);
+            store_words<W>(oa + 2 * W, opp[m]);
+            if (want_out) store_words<W>(oa + 3 * W, outm[m]);
+        };
+
+        if (obs_only) {
+            all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                                           wall, outm, team, opp, cnt);
+#pragma unroll
+            for (int m = 0; m < TPL; ++m)
+                if (mine_live[m]) store_obs(m);
+            return;
+        }
+
+        // One step from the generator's actions of this step (3 bits per
+        // agent); all of its stores are issued together at the end.
+        auto step = [&](uint64_t acts) __attribute__((always_inline)) {
+            // ---- 1 external actions override the drawn ones (-1 keeps the draw)
+            if (has_act) {
+                uint64_t ov = 0, om = 0;
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
-                    const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
-                    tgt[i] = pp[i] + dl;
+                    if (i < n) {
+                        const int v = act_p[i];
+                        if (v != -1) {
+                            const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                            ov |= (uint64_t)a << (3 * i);
+                            om |= 7ull << (3 * i);
+                        }
+                    }
+                }
+                acts = (acts & ~om) | ov;
+                act_p += J.agent_stride;
+            }
+            acts &= amask;
+
+            // ---- 2 moves, agent-index order (redundant in every lane of the env)
+            int tgt[NMAX];
+            bool open[NMAX];
+#pragma unroll
+            for (int i = 0; i < NMAX; ++i) {
+                const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
+                const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
+                tgt[i] = pp[i] + dl;
+                if constexpr (NBR) {
+                    open[i] = ((nbw >> (5u * (uint32_t)i + a)) & 1u) == 0u;
+                } else {
                     uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)P + (((uint32_t)tgt[i] >> 5) & 7u);
                     widx = widx < last_word ? widx : last_word;
                     const uint32_t wbit = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
                     open[i] = a != 0u && wbit == 0u;
                 }
-#pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    bool clash = false;
-#pragma unroll
-                    for (int jj = 0; jj < NMAX; ++jj)
-                        if (jj != i) clash = clash || pp[jj] == tgt[i];
-                    pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
-                }
-                own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-
-                // ---- 3 detection (from the channels of the post-move positions)
-                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                           wall, outm, team, opp, cnt);
-                uint32_t seen_h = 0;
-#pragma unroll
-                for (int m = 0; m < TPL; ++m) {
-                    const int a = l + m * LANES;
-                    const bool sa = a < S;
-                    if (active && a < n) rew_p[a] = (float)(sa ? cnt[m] : -cnt[m]);
-                    seen_h |= (a < n && !sa && cnt[m] > 0) ? (1u << a) : 0u;
-                }
-                found |= group_or_dpp<LANES>(seen_h);
-
-                // ---- 4 termination / truncation
-                t += 1u;
-                const bool term = (flags & 2u) && n > S && (found & hmask) == hmask;
-                const bool trunc = t >= Lep;
-                const uint32_t d = (term ? 1u : 0u) | (trunc ? 2u : 0u);
-                if (active && l == 0) *done_p = (uint8_t)d;
-
-                // ---- 5 same-step auto-reset from the unchanged grid
-                if (d) {
-                    ep += 1u;
-                    t = 0u;
-                    found = 0u;
-                    spawn_agents(spawned, n, H, Wd, slot, P, env, k0, k1, ep);
-                    wave_lds_fence();
-#pragma unroll
-                    for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
-                    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-                    all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S,
-                                               want_out, wall, outm, team, opp, cnt);
-                }
-
-                // ---- 6 generator step key
-                steps += 1u;
-                j = (j + 1 == kb) ? 0 : j + 1;
-                rew_p += J.agent_stride;
-                done_p += J.env_stride;
-            } else {
-                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                           wall, outm, team, opp, cnt);
             }
+#pragma unroll
+            for (int i = 0; i < NMAX; ++i) {
+                bool clash = false;
+#pragma unroll
+                for (int jj = 0; jj < NMAX; ++jj)
+                    if (jj != i) clash = clash || pp[jj] == tgt[i];
+                pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
+            }
+            own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
-            // ---- 7 observations of this lane's agents (channel-major words)
+            // ---- 3 detection (from the channels of the post-move positions)
+            all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                                           wall, outm, team, opp, cnt);
+            uint32_t seen_h = 0;
+            float rv[TPL];
 #pragma unroll
             for (int m = 0; m < TPL; ++m) {
-                const int a = l + m * LANES;
-                if (active && a < n) {
-                    GAS uint32_t *oa = obs_p + (uint32_t)(a * C * W);
-                    store_words<W>(oa, wall[m]);
-                    store_words<W>(oa + W, team[m]);
-                    store_words<W>(oa + 2 * W, opp[m]);
-                    if (want_out) store_words<W>(oa + 3 * W, outm[m]);
+                rv[m] = (float)(rsign[m] * cnt[m]);
+                seen_h |= cnt[m] > 0 ? hbit[m] : 0u;
+            }
+            found |= group_or_dpp<LANES>(seen_h);
+
+            // ---- 4 termination / truncation
+            t += 1u;
+            const uint32_t d = ((found & tmask) == tmask ? 1u : 0u) | (t >= Lep ? 2u : 0u);
+
+            // ---- 5 same-step auto-reset from the unchanged grid
+            if (d) {
+                ep += 1u;
+                t = 0u;
+                found = 0u;
+                spawn_agents(spawned, n, H, Wd, slot, P, env, k0, k1, ep);
+                wave_lds_fence();
+#pragma unroll
+                for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
+                own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                                               wall, outm, team, opp, cnt);
+            }
+            steps += 1u;
+            if constexpr (NBR)
+                nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field<R, W>(wall[m]); });
+
+            // ---- 6 outputs: observations of this lane's agents (channel-major
+            // words, after the reset), their rewards, and the env's done flag
+            // (every lane of the env with an agent writes the same byte)
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                if (mine_live[m]) {
+                    store_obs(m);
+                    rew_p[l + m * LANES] = rv[m];
+                    if (m == 0) *done_p = (uint8_t)d;
                 }
             }
             obs_p += J.obs_stride;
-        }
+            rew_p += J.agent_stride;
+            done_p += J.env_stride;
+        };
 
+        // action words of this lane's generator block: 4 draws mapped to 0..4
+        auto block_actions = [&](uint32_t sub, uint32_t step) __attribute__((always_inline)) {
+            const U4 x = philox(env, (ST_ACTION << 24) | sub, step, 0u, k0, k1);
+            return range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) | (range_map(x.z, 5u) << 6) |
+                   (range_map(x.w, 5u) << 9);
+        };
+
+        if constexpr (DPP_WINDOW) {
+            // lane l draws the block of step steps + l; a window covers LANES steps
+            if constexpr (UNROLL) {
+                uint32_t k = 0;
+                for (; k + LANES <= nsteps; k += LANES) {
+                    const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+#pragma unroll
+                    for (int jw = 0; jw < LANES; ++jw) step((w >> (12 * jw)) & 0xfffull);
+                }
+                if (k < nsteps) {
+                    const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+                    for (uint32_t jw = 0; k < nsteps; ++k, ++jw) step((w >> (12u * jw)) & 0xfffull);
+                }
+            } else {
+                uint64_t w = 0;
+                for (uint32_t k = 0; k < nsteps; ++k) {
+                    const uint32_t jw = k & (uint32_t)(LANES - 1);
+                    if (jw == 0u) w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+                    step((w >> (12u * jw)) & 0xfffull);
+                }
+            }
+        } else if constexpr (WINDOWED) {
+            // lane l draws block (step + wstep, group wgroup) of the window
+            uint32_t win = 0;
+            int j = 0;
+            for (uint32_t k = 0; k < nsteps; ++k) {
+                if (j == 0) win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                uint64_t acts = 0;
+#pragma unroll
+                for (int g = 0; g < MAXCALLS; ++g) {
+                    if (g < ncalls) {
+                        const uint32_t v = (uint32_t)__shfl((int)win, q * LANES + j * ncalls + g, 64);
+                        acts |= (uint64_t)v << (12 * g);
+                    }
+                }
+                step(acts);
+                j = (j + 1 == kb) ? 0 : j + 1;
+            }
+        } else {
+            for (uint32_t k = 0; k < nsteps; ++k) {
+                uint64_t acts = 0;
+#pragma unroll
+                for (int g = 0; g < MAXCALLS; ++g)
+                    if (g < ncalls) acts |= (uint64_t)block_actions((uint32_t)g, steps) << (12 * g);
+                step(acts);
+            }
+        }
     };
     if (collide)
         run(std::false_type{});
@@ -630,7 +724,7 @@ __global__ __launch_bounds__(64) void step_kernel(const Tile *__restrict__ tiles
     if (blockIdx.x >= n_tiles) return;
     const Tile tile = tiles[blockIdx.x];
     const JobDesc J = jobs ? jobs[tile.job] : job0;
-    step_tile<LANES, NMAX, R>(tile, J, K, step_base, slot_words, lds);
+    step_tile<LANES, NMAX, R, true>(tile, J, K, step_base, slot_words, lds);
 }
 
 // Variant code of a tile: agent-count bucket * 4 + radius - 1.
@@ -643,10 +737,10 @@ __device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobD
     constexpr int NMAX = BUCKET_NMAX[B];
     if constexpr ((NMAX + LANES - 1) / LANES <= 4) {
         switch (r) {
-        case 1: step_tile<LANES, NMAX, 1>(tile, J, K, step_base, slot_words, lds); break;
-        case 2: step_tile<LANES, NMAX, 2>(tile, J, K, step_base, slot_words, lds); break;
-        case 3: step_tile<LANES, NMAX, 3>(tile, J, K, step_base, slot_words, lds); break;
-        default: step_tile<LANES, NMAX, 4>(tile, J, K, step_base, slot_words, lds); break;
+        case 1: step_tile<LANES, NMAX, 1, false>(tile, J, K, step_base, slot_words, lds); break;
+        case 2: step_tile<LANES, NMAX, 2, false>(tile, J, K, step_base, slot_words, lds); break;
+        case 3: step_tile<LANES, NMAX, 3, false>(tile, J, K, step_base, slot_words, lds); break;
+        default: step_tile<LANES, NMAX, 4, false>(tile, J, K, step_base, slot_words, lds); break;
         }
     }
 }

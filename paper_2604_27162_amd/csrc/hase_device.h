@@ -414,8 +414,12 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // spans exactly LANES steps
     constexpr bool DPP_WINDOW = WINDOWED && NMAX <= 4 && (LANES == 2 || LANES == 4);
     // with at most 4 agents the wall tests of the moves come from bits kept
-    // from the previous step's windows instead of board reads
+    // from the previous step's windows instead of board reads, and detection
+    // (rewards, found bits) is a pairwise Chebyshev test in every lane of the
+    // env, independent of the observation masks
     constexpr bool NBR = NMAX <= 4;
+    constexpr bool PAIRS = NMAX <= 4;
+    constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
 
     const int lane = (int)threadIdx.x;
     const int q = lane / LANES;  // env slot in the tile
@@ -512,6 +516,29 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // termination needs every hider found; without capture-ends (or without
     // hiders) the test uses bit 31, which no agent sets
     const uint32_t tmask = ((flags & 2u) && n > S) ? hmask : 0x80000000u;
+    const uint32_t cmask = collide ? 1u : 0u;
+    // pair constants (PAIRS): pair (i, j) has opposite roles iff i < S <= j,
+    // its hider is j; pinv[m] has the bits of such pairs that involve the
+    // task's agent
+    uint32_t pair_hb[NP], pinv[TPL];
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) pinv[m] = 0u;
+    if constexpr (PAIRS) {
+        int pi = 0;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+#pragma unroll
+            for (int jj = i + 1; jj < NMAX; ++jj, ++pi) {
+                const bool opp_ij = i < S && S <= jj && jj < n;
+                pair_hb[pi] = opp_ij ? 1u << jj : 0u;
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int a = l + m * LANES;
+                    pinv[m] |= (opp_ij && (a == i || a == jj)) ? 1u << pi : 0u;
+                }
+            }
+        }
+    }
 
     // The step loop, instantiated for channels computed assuming distinct
     // agent cells (collisions on) and for the exact per-agent test; the choice
@@ -561,43 +588,78 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             acts &= amask;
 
             // ---- 2 moves, agent-index order (redundant in every lane of the env)
-            int tgt[NMAX];
-            bool open[NMAX];
+            if constexpr (NBR) {
+                // Integer decisions only: lane-mask logic would cost a round
+                // trip through the scalar unit on the step's critical path. A
+                // move is blocked by its field bit or, with collisions on, by
+                // an agent on the target (cells are below 2^16, so
+                // ((c ^ c') - 1) >> 31 is 1 exactly when c == c').
 #pragma unroll
-            for (int i = 0; i < NMAX; ++i) {
-                const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
-                const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
-                tgt[i] = pp[i] + dl;
-                if constexpr (NBR) {
-                    open[i] = ((nbw >> (5u * (uint32_t)i + a)) & 1u) == 0u;
-                } else {
+                for (int i = 0; i < NMAX; ++i) {
+                    const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
+                    const int tg = pp[i] + (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
+                    uint32_t occ = 0u;
+#pragma unroll
+                    for (int jj = 0; jj < NMAX; ++jj)
+                        if (jj != i) occ |= ((uint32_t)(tg ^ pp[jj]) - 1u) >> 31;
+                    const uint32_t blk = ((nbw >> (5u * (uint32_t)i + a)) & 1u) | (occ & cmask);
+                    pp[i] = blk ? pp[i] : tg;
+                }
+            } else {
+                int tgt[NMAX];
+                bool open[NMAX];
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
+                    const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
+                    tgt[i] = pp[i] + dl;
                     uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)P + (((uint32_t)tgt[i] >> 5) & 7u);
                     widx = widx < last_word ? widx : last_word;
                     const uint32_t wbit = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
                     open[i] = a != 0u && wbit == 0u;
                 }
-            }
 #pragma unroll
-            for (int i = 0; i < NMAX; ++i) {
-                bool clash = false;
+                for (int i = 0; i < NMAX; ++i) {
+                    bool clash = false;
 #pragma unroll
-                for (int jj = 0; jj < NMAX; ++jj)
-                    if (jj != i) clash = clash || pp[jj] == tgt[i];
-                pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
+                    for (int jj = 0; jj < NMAX; ++jj)
+                        if (jj != i) clash = clash || pp[jj] == tgt[i];
+                    pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
+                }
             }
             own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
-            // ---- 3 detection (from the channels of the post-move positions)
+            // ---- 3 detection at the post-move positions, and the channels
             all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                            wall, outm, team, opp, cnt);
-            uint32_t seen_h = 0;
             float rv[TPL];
+            if constexpr (PAIRS) {
+                uint32_t near = 0u, seen_h = 0u;
+                int pi = 0;
 #pragma unroll
-            for (int m = 0; m < TPL; ++m) {
-                rv[m] = (float)(rsign[m] * cnt[m]);
-                seen_h |= cnt[m] > 0 ? hbit[m] : 0u;
+                for (int i = 0; i < NMAX; ++i) {
+#pragma unroll
+                    for (int jj = i + 1; jj < NMAX; ++jj, ++pi) {
+                        const uint32_t dx = (uint32_t)((pp[i] & 0xff) - (pp[jj] & 0xff) + R);
+                        const uint32_t dy = (uint32_t)((pp[i] >> 8) - (pp[jj] >> 8) + R);
+                        const bool in = (dx > dy ? dx : dy) < (uint32_t)D;
+                        near |= in ? 1u << pi : 0u;
+                        seen_h |= in ? pair_hb[pi] : 0u;
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < TPL; ++m)
+                    rv[m] = (float)(rsign[m] * __builtin_popcount(near & pinv[m]));
+                found |= seen_h;
+            } else {
+                uint32_t seen_h = 0u;
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    rv[m] = (float)(rsign[m] * cnt[m]);
+                    seen_h |= cnt[m] > 0 ? hbit[m] : 0u;
+                }
+                found |= group_or_dpp<LANES>(seen_h);
             }
-            found |= group_or_dpp<LANES>(seen_h);
 
             // ---- 4 termination / truncation
             t += 1u;

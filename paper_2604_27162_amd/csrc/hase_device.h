@@ -665,7 +665,25 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             t += 1u;
             const uint32_t d = ((found & tmask) == tmask ? 1u : 0u) | (t >= Lep ? 2u : 0u);
 
-            // ---- 5 same-step auto-reset from the unchanged grid
+            // ---- 5 outputs, assuming no reset: observations of this lane's
+            // agents (channel-major words), their rewards, and the env's done
+            // flag. Issuing them before the reset test lets the scheduler mix
+            // them into the step's dependency chains.
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                if (mine_live[m]) {
+                    store_obs(m);
+                    rew_p[l + m * LANES] = rv[m];
+                    if (m == 0) *done_p = (uint8_t)d;
+                }
+            }
+            if constexpr (NBR)
+                nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field<R, W>(wall[m]); });
+
+            // ---- 6 same-step auto-reset from the unchanged grid; the env's
+            // observation is written again (a later store to the same words
+            // by the same lane) from the respawned positions. d is the same in
+            // every lane of an env, so the DPP gather inside sees whole groups.
             if (d) {
                 ep += 1u;
                 t = 0u;
@@ -677,22 +695,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
                 all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                                wall, outm, team, opp, cnt);
+#pragma unroll
+                for (int m = 0; m < TPL; ++m)
+                    if (mine_live[m]) store_obs(m);
+                if constexpr (NBR)
+                    nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field<R, W>(wall[m]); });
             }
             steps += 1u;
-            if constexpr (NBR)
-                nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field<R, W>(wall[m]); });
-
-            // ---- 6 outputs: observations of this lane's agents (channel-major
-            // words, after the reset), their rewards, and the env's done flag
-            // (every lane of the env with an agent writes the same byte)
-#pragma unroll
-            for (int m = 0; m < TPL; ++m) {
-                if (mine_live[m]) {
-                    store_obs(m);
-                    rew_p[l + m * LANES] = rv[m];
-                    if (m == 0) *done_p = (uint8_t)d;
-                }
-            }
             obs_p += J.obs_stride;
             rew_p += J.agent_stride;
             done_p += J.env_stride;

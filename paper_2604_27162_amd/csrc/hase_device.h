@@ -78,11 +78,12 @@ __device__ __forceinline__ const GAS T *gp(const T *p)
     return (const GAS T *)p;
 }
 
-// Bit of the padded board at packed padded cell pc = y' << 8 | x'.
-__device__ __forceinline__ uint32_t board_bit(const uint32_t *slot, int P, int pc)
+// Bit of the padded board in LDS (rows of LDS_ROW words) at packed padded
+// cell pc = y' << 8 | x'.
+__device__ __forceinline__ uint32_t board_bit(const uint32_t *slot, int pc)
 {
     const int yy = pc >> 8, xx = pc & 0xff;
-    return (slot[yy * P + (xx >> 5)] >> (xx & 31)) & 1u;
+    return (slot[yy * LDS_ROW + (xx >> 5)] >> (xx & 31)) & 1u;
 }
 
 // Agent spawn for episode ep: agents in index order, up to 64 uniform draws
@@ -92,8 +93,7 @@ __device__ __forceinline__ uint32_t board_bit(const uint32_t *slot, int P, int p
 // to out[0..n) in LDS; the loops are not unrolled (spawning is rare), and all
 // lanes of an env may run it together since they write identical values.
 __device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, const uint32_t *slot,
-                                             int P, uint32_t env, uint32_t k0, uint32_t k1,
-                                             uint32_t ep)
+                                             uint32_t env, uint32_t k0, uint32_t k1, uint32_t ep)
 {
     const uint32_t cells = (uint32_t)(H * W);
     for (int i = 0; i < n; ++i) {
@@ -104,7 +104,7 @@ __device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, cons
             c = range_map(x.x, cells);
             const uint32_t y = c / (uint32_t)W, xx = c - y * (uint32_t)W;
             const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
-            bool ok = board_bit(slot, P, pc) == 0u;
+            bool ok = board_bit(slot, pc) == 0u;
             for (int k = 0; k < i && ok; ++k) ok = out[k] != pc;
             if (ok) {
                 out[i] = pc;
@@ -116,7 +116,7 @@ __device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, cons
             if (cc >= cells) cc -= cells;
             const uint32_t y = cc / (uint32_t)W, xx = cc - y * (uint32_t)W;
             const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
-            bool ok = board_bit(slot, P, pc) == 0u;
+            bool ok = board_bit(slot, pc) == 0u;
             for (int k = 0; k < i && ok; ++k) ok = out[k] != pc;
             if (ok) {
                 out[i] = pc;
@@ -155,19 +155,18 @@ __device__ __forceinline__ void wave_lds_fence()
 // fully unrolled for radius R: wall|outside from the padded board and, for
 // 4-channel envs, outside-the-map only.
 template <int R, int W>
-__device__ __forceinline__ void window_rows(const uint32_t *slot, int P, int H, int Wd, int ax,
-                                            int ay, bool want_out, uint32_t (&wall)[W],
-                                            uint32_t (&outm)[W])
+__device__ __forceinline__ void window_rows(const uint32_t *slot, int H, int Wd, int ax, int ay,
+                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W])
 {
     constexpr int D = 2 * R + 1;
     constexpr uint32_t DM = (1u << D) - 1u;
     const int col = ax - R;  // padded column of the window's left edge
-    // ay - R >= PAD - R >= 0: a 24-bit multiply suffices
-    const uint32_t *base = slot + __umul24((uint32_t)(ay - R), (uint32_t)P) + (col >> 5);
+    // one base address; the rows are at constant offsets from it
+    const uint32_t *base = slot + (ay - R) * LDS_ROW + (col >> 5);
     const uint32_t sh = (uint32_t)(col & 31);
 #pragma unroll
     for (int rho = 0; rho < D; ++rho) {
-        const uint32_t *rp = base + rho * P;
+        const uint32_t *rp = base + rho * LDS_ROW;
         const uint32_t bits = __builtin_amdgcn_alignbit(rp[1], rp[0], sh) & DM;
         const int off = rho * D, wi = off >> 5, b = off & 31;
         wall[wi] |= bits << b;
@@ -265,7 +264,7 @@ constexpr uint64_t MOVE_TABLE = 0x101ull | (0x001ull << 12) | (0x201ull << 24) |
 // every other agent by index. Returns the number of other-role agents in the
 // window (Chebyshev distance <= R).
 template <int R, int W, int NMAX, bool EXACT>
-__device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, int Wd,
+__device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
                                            const int (&pp)[NMAX], int a, int pa, int n, int S,
                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
                                            uint32_t (&team)[W], uint32_t (&opp)[W])
@@ -275,7 +274,7 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, i
 #pragma unroll
     for (int i = 0; i < W; ++i) wall[i] = outm[i] = team[i] = opp[i] = 0u;
     const int ax = pa & 0xff, ay = pa >> 8;
-    window_rows<R, W>(slot, P, H, Wd, ax, ay, want_out, wall, outm);
+    window_rows<R, W>(slot, H, Wd, ax, ay, want_out, wall, outm);
     const bool sa = a < S;
     if constexpr (!EXACT) {
         // bits of all agents in the window, and of the seekers among them;
@@ -345,7 +344,7 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int P, int H, i
 }
 
 template <int R, int W, int NMAX, int TPL, bool EXACT>
-__device__ __forceinline__ void all_masks(const uint32_t *slot, int P, int H, int Wd,
+__device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
                                           const int (&pp)[NMAX], int l, int lanes,
                                           const int (&mine)[TPL], int n, int S, bool want_out,
                                           uint32_t (&wall)[TPL][W], uint32_t (&outm)[TPL][W],
@@ -354,7 +353,7 @@ __device__ __forceinline__ void all_masks(const uint32_t *slot, int P, int H, in
 {
 #pragma unroll
     for (int m = 0; m < TPL; ++m)
-        cnt[m] = agent_masks<R, W, NMAX, EXACT>(slot, P, H, Wd, pp, l + m * lanes, mine[m], n, S,
+        cnt[m] = agent_masks<R, W, NMAX, EXACT>(slot, H, Wd, pp, l + m * lanes, mine[m], n, S,
                                                 want_out, wall[m], outm[m], team[m], opp[m]);
 }
 
@@ -370,10 +369,10 @@ __device__ __forceinline__ uint32_t blocked_field(const uint32_t (&wall)[W])
     return 1u | (bit(C - D) << 1) | (bit(C + D) << 2) | (bit(C + 1) << 3) | (bit(C - 1) << 4);
 }
 
-__device__ __forceinline__ uint32_t blocked_field_board(const uint32_t *slot, int P, int pa)
+__device__ __forceinline__ uint32_t blocked_field_board(const uint32_t *slot, int pa)
 {
-    return 1u | (board_bit(slot, P, pa - 256) << 1) | (board_bit(slot, P, pa + 256) << 2) |
-           (board_bit(slot, P, pa + 1) << 3) | (board_bit(slot, P, pa - 1) << 4);
+    return 1u | (board_bit(slot, pa - 256) << 1) | (board_bit(slot, pa + 256) << 2) |
+           (board_bit(slot, pa + 1) << 3) | (board_bit(slot, pa - 1) << 4);
 }
 
 // Fields of agents 0..NMAX-1 (NMAX <= 6) at bits 5a.., gathered from the
@@ -449,9 +448,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     uint32_t *slot = lds + (uint32_t)q * (slot_words + MAX_AGENTS);
     int *spawned = (int *)(slot + slot_words);
     {
+        // rows of P words in HBM -> rows of LDS_ROW words (unused words 0)
         const GAS uint32_t *src = gp(J.bb) + gp(J.tab.bb_off)[e];
-        const int bw = (H + 2 * PAD) * P + 1;
-        for (int i = l; i < bw; i += LANES) slot[i] = src[i];
+        const int bw = (H + 2 * PAD) * LDS_ROW + 1;
+        for (int i = l; i < bw; i += LANES) {
+            const int y = i / LDS_ROW, x = i - y * LDS_ROW;
+            slot[i] = x < P ? src[y * P + x] : 0u;
+        }
     }
     const uint32_t last_word = slot_words - 1u;
 
@@ -498,7 +501,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // blocked-move fields of all agents at their current cells (NBR only)
     uint32_t nbw = 0;
     if constexpr (NBR)
-        nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field_board(slot, P, mine[m]); });
+        nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field_board(slot, mine[m]); });
 
     const bool has_act = J.act != nullptr;
     // per-task constants: the task's agent exists (and its env is active), its
@@ -557,7 +560,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         };
 
         if (obs_only) {
-            all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+            all_masks<R, W, NMAX, TPL, EX>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                            wall, outm, team, opp, cnt);
 #pragma unroll
             for (int m = 0; m < TPL; ++m)
@@ -613,7 +616,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
                     const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
                     tgt[i] = pp[i] + dl;
-                    uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)P + (((uint32_t)tgt[i] >> 5) & 7u);
+                    uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)LDS_ROW + (((uint32_t)tgt[i] >> 5) & 7u);
                     widx = widx < last_word ? widx : last_word;
                     const uint32_t wbit = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
                     open[i] = a != 0u && wbit == 0u;
@@ -630,7 +633,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
             // ---- 3 detection at the post-move positions, and the channels
-            all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+            all_masks<R, W, NMAX, TPL, EX>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                            wall, outm, team, opp, cnt);
             float rv[TPL];
             if constexpr (PAIRS) {
@@ -688,12 +691,12 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 ep += 1u;
                 t = 0u;
                 found = 0u;
-                spawn_agents(spawned, n, H, Wd, slot, P, env, k0, k1, ep);
+                spawn_agents(spawned, n, H, Wd, slot, env, k0, k1, ep);
                 wave_lds_fence();
 #pragma unroll
                 for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
                 own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-                all_masks<R, W, NMAX, TPL, EX>(slot, P, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                all_masks<R, W, NMAX, TPL, EX>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                                wall, outm, team, opp, cnt);
 #pragma unroll
                 for (int m = 0; m < TPL; ++m)

@@ -28,6 +28,12 @@ inline int board_words_per_row(int W) { return (W + 2 * PAD + 31) >> 5; }
 // at the last row stays inside the slot
 inline int board_words(int H, int W) { return (H + 2 * PAD) * board_words_per_row(W) + 1; }
 
+// In LDS every board row takes LDS_ROW words whatever the width (the widest
+// padded row, MAX_SIDE + 2 PAD = 72 cells, needs 3), so row offsets are
+// compile-time constants of the step kernel; plus one slack word.
+constexpr int LDS_ROW = 3;
+inline int lds_board_words(int H) { return (H + 2 * PAD) * LDS_ROW + 1; }
+
 // Packed per-env spec words.
 //   spec0 = H | W << 8 | n << 16 | S << 24
 //   spec1 = r | C << 4 | flags << 8 | L << 16

@@ -13,7 +13,7 @@ namespace hase {
 __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
 {
     __shared__ uint8_t cellw[MAX_SIDE * MAX_SIDE];
-    __shared__ uint32_t board[(MAX_SIDE + 2 * PAD) * 3 + 1];
+    __shared__ uint32_t board[(MAX_SIDE + 2 * PAD) * LDS_ROW + 1];
     __shared__ int spawned[MAX_AGENTS];
     const uint32_t e = blockIdx.x;
     const int lane = (int)threadIdx.x;
@@ -49,12 +49,16 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
     }
     __syncthreads();
 
+    // HBM board: rows of P words; the LDS copy used by the spawn below has
+    // rows of LDS_ROW words (unused words 0), as in the step kernel
     const int rows = H + 2 * PAD;
     const int bw = rows * P + 1;
+    for (int i = lane; i < rows * LDS_ROW + 1; i += 64) board[i] = 0u;
+    __syncthreads();
     for (int i = lane; i < bw; i += 64) {
         uint32_t word = 0xffffffffu;  // slack word
+        const int yy = i / P, j = i - (i / P) * P;
         if (i < rows * P) {
-            const int yy = i / P, j = i - (i / P) * P;
             word = 0;
             for (int b = 0; b < 32; ++b) {
                 const int xx = 32 * j + b;
@@ -63,8 +67,10 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
                 if (!out) v = cellw[(yy - PAD) * W + (xx - PAD)] != 0;
                 word |= (v ? 1u : 0u) << b;
             }
+            board[yy * LDS_ROW + j] = word;
+        } else {
+            board[rows * LDS_ROW] = word;
         }
-        board[i] = word;
         A.bb[A.tab.bb_off[e] + (uint32_t)i] = word;
     }
     __syncthreads();
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
         return;
     }
     if (lane == 0) {
-        spawn_agents(spawned, n, H, W, board, P, env, k0, k1, 0u);
+        spawn_agents(spawned, n, H, W, board, env, k0, k1, 0u);
         const uint32_t ao = A.tab.agent_off[e];
         for (int j = 0; j < n; ++j) {
             const uint32_t x = (uint32_t)(spawned[j] & 0xff) - PAD, y = (uint32_t)(spawned[j] >> 8) - PAD;

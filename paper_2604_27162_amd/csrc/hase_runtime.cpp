@@ -256,8 +256,7 @@ int build_tiles(hase_batch *b)
                 const uint32_t base = (uint32_t)perm.size();
                 for (uint32_t e : ids) {
                     perm.push_back(e);
-                    grp.slot_words = std::max(grp.slot_words,
-                                              (uint32_t)board_words(p.specs[e].height, p.specs[e].width));
+                    grp.slot_words = std::max(grp.slot_words, (uint32_t)lds_board_words(p.specs[e].height));
                 }
                 for (uint32_t i = 0; i < ids.size(); i += E) {
                     Tile t;

@@ -276,7 +276,50 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
     const int ax = pa & 0xff, ay = pa >> 8;
     window_rows<R, W>(slot, H, Wd, ax, ay, want_out, wall, outm);
     const bool sa = a < S;
-    if constexpr (!EXACT) {
+    if constexpr (!EXACT && NMAX <= 4) {
+        // Distinct cells: the agent itself is the centre (in no channel) and
+        // the others are the NMAX - 1 agents k (k < a) or k + 1 (k >= a). One
+        // packed difference u = (dy + R) << 8 | (dx + R) gives both the
+        // window test and the bit index (an agent outside the window makes
+        // a byte of u at least D: coordinates differ by less than 256 - D).
+        const uint32_t base = (uint32_t)(R * 256 + R) - (uint32_t)pa;
+        uint64_t tm = 0, op = 0;
+        uint32_t tm_hi = 0, op_hi = 0;  // window bits 64.. (radius 4 only)
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < NMAX - 1; ++k) {
+            const bool up = k >= a;
+            const uint32_t u = (uint32_t)(up ? pp[k + 1] : pp[k]) + base;
+            const bool same = ((up ? k + 1 : k) < S) == sa;
+            const uint32_t lo = u & 0xffu, hi = u >> 8;
+            const bool in = (lo > hi ? lo : hi) < (uint32_t)D;
+            const uint32_t kk = (uint32_t)__umul24(hi, (uint32_t)D) + lo;
+            if constexpr (W <= 2) {
+                const uint64_t bit = in ? (1ull << (kk & 63u)) : 0ull;
+                tm |= same ? bit : 0ull;
+                op |= same ? 0ull : bit;
+            } else {
+                const uint64_t bit = (in && kk < 64u) ? (1ull << (kk & 63u)) : 0ull;
+                const uint32_t bh = (in && kk >= 64u) ? (1u << (kk & 31u)) : 0u;
+                tm |= same ? bit : 0ull;
+                op |= same ? 0ull : bit;
+                tm_hi |= same ? bh : 0u;
+                op_hi |= same ? 0u : bh;
+            }
+            cnt += (in && !same) ? 1 : 0;
+        }
+        team[0] = (uint32_t)tm;
+        opp[0] = (uint32_t)op;
+        if constexpr (W >= 2) {
+            team[1] = (uint32_t)(tm >> 32);
+            opp[1] = (uint32_t)(op >> 32);
+        }
+        if constexpr (W == 3) {
+            team[2] = tm_hi;
+            opp[2] = op_hi;
+        }
+        return cnt;
+    } else if constexpr (!EXACT) {
         // bits of all agents in the window, and of the seekers among them;
         // one select per bit (a 64-bit shift), so no scalar mask logic
         uint64_t all_lo = 0, sk_lo = 0;

@@ -215,7 +215,12 @@ __device__ __forceinline__ void own_positions(const int (&pp)[NMAX], int l, int 
 {
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
-        const int a = l + m * LANES;
+        int a = l + m * LANES;
+        // With many agents the compares a == i, hoisted out of the step loop
+        // as lane masks, would not fit the scalar registers (they would be
+        // spilled to vector lanes and read back every step): an empty asm
+        // makes a opaque here, so each compare is redone on the vector unit.
+        if constexpr (NMAX > 4) asm volatile("" : "+v"(a));
         int v = pp[0];
 #pragma unroll
         for (int i = 1; i < NMAX; ++i) v = (a == i) ? pp[i] : v;
@@ -320,41 +325,44 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
         }
         return cnt;
     } else if constexpr (!EXACT) {
-        // bits of all agents in the window, and of the seekers among them;
-        // one select per bit (a 64-bit shift), so no scalar mask logic
-        uint64_t all_lo = 0, sk_lo = 0;
+        // Bits of all agents in the window, and of the seekers among them,
+        // from the packed difference u = (dy + R) << 8 | (dx + R) (see above);
+        // a shifted 0/1 word carries the window test, and the seeker masks
+        // are loop-invariant words, so no lane-mask logic is needed.
+        const uint32_t base = (uint32_t)(R * 256 + R) - (uint32_t)pa;
+        uint64_t all = 0, sk = 0;
         uint32_t all_hi = 0, sk_hi = 0;  // window bits 64.. (radius 4 only)
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) {
-            const uint32_t dx = (uint32_t)((pp[j] & 0xff) - ax + R);
-            const uint32_t dy = (uint32_t)((pp[j] >> 8) - ay + R);
-            // only used when the agent is in the window (dx, dy < D)
-            const uint32_t kk = (uint32_t)__umul24(dy, (uint32_t)D) + dx;
-            const uint32_t m = dx > dy ? dx : dy;
-            const bool in = m < (uint32_t)D;
-            const bool js = j < S;
+            const uint32_t u = (uint32_t)pp[j] + base;
+            const uint32_t lo = u & 0xffu, hi = u >> 8;
+            const uint32_t in = (lo > hi ? lo : hi) < (uint32_t)D ? 1u : 0u;
+            const uint32_t kk = (uint32_t)__umul24(hi, (uint32_t)D) + lo;
+            const uint32_t skm = j < S ? 0xffffffffu : 0u;
+            const uint64_t skm64 = ((uint64_t)skm << 32) | skm;
+            const uint64_t bit = (uint64_t)in << (kk & 63u);
             if constexpr (W <= 2) {
-                const uint64_t bit = in ? (1ull << (kk & 63u)) : 0ull;
-                all_lo |= bit;
-                sk_lo |= js ? bit : 0ull;
+                all |= bit;
+                sk |= bit & skm64;
             } else {
-                const uint64_t bit = (in && kk < 64u) ? (1ull << (kk & 63u)) : 0ull;
-                const uint32_t bh = (in && kk >= 64u) ? (1u << (kk & 31u)) : 0u;
-                all_lo |= bit;
-                sk_lo |= js ? bit : 0ull;
-                all_hi |= bh;
-                sk_hi |= js ? bh : 0u;
+                const bool low = kk < 64u;
+                const uint64_t b01 = low ? bit : 0ull;
+                const uint32_t b2 = low ? 0u : (uint32_t)bit;
+                all |= b01;
+                sk |= b01 & skm64;
+                all_hi |= b2;
+                sk_hi |= b2 & skm;
             }
         }
-        const uint64_t hd_lo = all_lo & ~sk_lo;
-        const uint64_t tm_lo = sa ? sk_lo : hd_lo, op_lo = sa ? hd_lo : sk_lo;
-        team[0] = (uint32_t)tm_lo;
-        opp[0] = (uint32_t)op_lo;
-        int cnt = __builtin_popcount((uint32_t)op_lo);
+        const uint64_t hd = all & ~sk;
+        const uint64_t tm = sa ? sk : hd, op = sa ? hd : sk;
+        team[0] = (uint32_t)tm;
+        opp[0] = (uint32_t)op;
+        int cnt = __builtin_popcount((uint32_t)op);
         if constexpr (W >= 2) {
-            team[1] = (uint32_t)(tm_lo >> 32);
-            opp[1] = (uint32_t)(op_lo >> 32);
-            cnt += __builtin_popcount((uint32_t)(op_lo >> 32));
+            team[1] = (uint32_t)(tm >> 32);
+            opp[1] = (uint32_t)(op >> 32);
+            cnt += __builtin_popcount((uint32_t)(op >> 32));
         }
         if constexpr (W == 3) {
             const uint32_t hd_hi = all_hi & ~sk_hi;
@@ -652,25 +660,33 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     pp[i] = blk ? pp[i] : tg;
                 }
             } else {
+                // Board reads for every target first (one LDS round trip), then
+                // the sequential decisions with integer logic only. A target is
+                // occupied iff the minimum of target ^ cell over the other
+                // agents is 0; the part over agents that have not moved yet is
+                // taken ahead of the sequential chain. Staying needs no test:
+                // its target is the agent's own cell.
                 int tgt[NMAX];
-                bool open[NMAX];
+                uint32_t wblk[NMAX], mpre[NMAX];
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
                     const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;
-                    const int dl = (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
-                    tgt[i] = pp[i] + dl;
+                    tgt[i] = pp[i] + (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
                     uint32_t widx = (uint32_t)(tgt[i] >> 8) * (uint32_t)LDS_ROW + (((uint32_t)tgt[i] >> 5) & 7u);
                     widx = widx < last_word ? widx : last_word;
-                    const uint32_t wbit = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
-                    open[i] = a != 0u && wbit == 0u;
+                    wblk[i] = (slot[widx] >> ((uint32_t)tgt[i] & 31u)) & 1u;
+                    uint32_t mn = 0xffffu;  // cells are below 2^16
+#pragma unroll
+                    for (int jj = i + 1; jj < NMAX; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
+                    mpre[i] = mn;
                 }
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    bool clash = false;
+                    uint32_t mn = mpre[i];
 #pragma unroll
-                    for (int jj = 0; jj < NMAX; ++jj)
-                        if (jj != i) clash = clash || pp[jj] == tgt[i];
-                    pp[i] = (open[i] && !(collide && clash)) ? tgt[i] : pp[i];
+                    for (int jj = 0; jj < i; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
+                    const uint32_t blk = wblk[i] | (((mn - 1u) >> 31) & cmask);
+                    pp[i] = blk ? pp[i] : tgt[i];
                 }
             }
             own_positions<LANES, NMAX, TPL>(pp, l, n, mine);

@@ -168,7 +168,11 @@ int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0);
  *   d_rew      [n_steps][agents_total] float32
  *   d_done     [n_steps][n_envs] uint8
  *   mode       HASE_STEP_PERSISTENT or HASE_STEP_PER_LAUNCH (identical results)
- * Enqueued on the stream; output buffers must not overlap the state.
+ * Enqueued on the stream; output buffers must not overlap the state. A
+ * persistent call is one kernel launch per variant group (all n_steps
+ * inside): a batch with one group replays a captured graph, a batch with
+ * several launches them directly on forked streams joined back into the
+ * stream, so the groups run concurrently.
  */
 int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
               float *d_rew, uint8_t *d_done, uint32_t mode);
@@ -176,7 +180,8 @@ int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t
 /*
  * Capture (if not cached) the persistent step graph for exactly these
  * arguments without launching it, so a later hase_step with the same
- * arguments only replays it (no capture cost on the critical path). Same
+ * arguments only replays it (no capture cost on the critical path); for a
+ * batch with several variant groups it only creates the side streams. Same
  * argument rules as hase_step; enqueues nothing.
  */
 int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,

@@ -322,11 +322,13 @@ int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, h
             bool fork)
 {
     const Tile *tiles = b->at<Tile>(b->plan.reg.tiles);
+    // the fork point precedes every launch of the call, so no group waits for
+    // another one launched before it
+    if (fork && b->variants.size() > 1) HIP_TRY(hipEventRecord(b->fork_ev, stream));
     for (size_t i = 0; i < b->variants.size(); ++i) {
         const Variant &v = b->variants[i];
         hipStream_t s = stream;
         if (fork && i > 0) {
-            HIP_TRY(hipEventRecord(b->fork_ev, stream));
             HIP_TRY(hipStreamWaitEvent(b->side[i], b->fork_ev, 0));
             s = b->side[i];
         }
@@ -393,6 +395,8 @@ int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_
     return HASE_OK;
 }
 
+// One launch of the whole call: the captured graph (one kernel node per
+// variant group, groups on parallel branches) replayed on the stream.
 int persistent_step(hase_batch *b, const JobDesc &job, uint32_t n_steps)
 {
     hipGraphExec_t exec = nullptr;
@@ -630,8 +634,12 @@ int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t
         return fail(HASE_EINVAL, "unknown step mode %u", mode);
     const JobDesc job = make_job(b, d_actions, d_obs, d_rew, d_done);
     if (mode == HASE_STEP_PERSISTENT) return persistent_step(b, job, n_steps);
+    if (b->variants.size() > 1) {
+        const int rc = ensure_streams(b);
+        if (rc) return rc;
+    }
     for (uint32_t k = 0; k < n_steps; ++k) {
-        const int rc = enqueue(b, job, 1, k, b->stream, false);
+        const int rc = enqueue(b, job, 1, k, b->stream, b->variants.size() > 1);
         if (rc) return rc;
     }
     return HASE_OK;

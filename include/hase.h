@@ -225,7 +225,9 @@ int hase_autotune(hase_batch *b, uint32_t n_steps, uint32_t *d_obs, float *d_rew
  * takes io[i].n_steps <= n_steps steps; its outputs (and optional actions)
  * are indexed by output step io[i].out_step0 + k in its own buffers, laid out
  * as for hase_step. Handles must be distinct and not in use elsewhere; the
- * work is enqueued on `stream` (a hipStream_t). d_workspace is caller device
+ * work is enqueued on `stream` (a hipStream_t): with more than one lanes
+ * value the launches run concurrently on side streams of io[0].batch,
+ * forked from and joined back into `stream`. d_workspace is caller device
  * memory of hase_multi_workspace bytes (job and tile tables), which must stay
  * untouched until the launch completes.
  */

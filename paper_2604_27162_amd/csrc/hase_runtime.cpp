@@ -874,14 +874,32 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
                            hipMemcpyHostToDevice, st));
     const JobDesc *djobs = reinterpret_cast<const JobDesc *>(ws);
     const Tile *dtiles = reinterpret_cast<const Tile *>(ws + jobs_bytes);
-    for (const Group &g : groups) {
+    // several groups run concurrently on the first request's side streams,
+    // forked after the uploads and joined back into the stream
+    hase_batch *fb = bs[0];
+    const bool fork = groups.size() > 1;
+    if (fork) {
+        rc = ensure_streams(fb);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(fb->fork_ev, st));
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group &g = groups[gi];
+        hipStream_t s = st;
+        if (fork && gi > 0) {
+            HIP_TRY(hipStreamWaitEvent(fb->side[gi], fb->fork_ev, 0));
+            s = fb->side[gi];
+        }
         if (g.mixed)
             HIP_TRY(launch_mixed((int)g.lanes, dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps,
-                                 0, g.slot, st));
+                                 0, g.slot, s));
         else
             HIP_TRY(launch_step((int)g.lanes, BUCKET_NMAX[g.code0 >> 2], (int)(g.code0 & 3u) + 1,
-                                dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps, 0, g.slot,
-                                st));
+                                dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps, 0, g.slot, s));
+        if (fork && gi > 0) {
+            HIP_TRY(hipEventRecord(fb->join_ev[gi], s));
+            HIP_TRY(hipStreamWaitEvent(st, fb->join_ev[gi], 0));
+        }
     }
     return HASE_OK;
 }

@@ -37,6 +37,15 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
+// a ^ b ^ c in one instruction (gfx950 three-input bitwise op, truth table
+// 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint32_t k0, uint32_t k1)
 {
@@ -44,8 +53,8 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -602,8 +611,16 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W];
         int cnt[TPL];
 
+        // this lane's output addresses of the current step, advanced per step
+        GAS uint32_t *obs_l[TPL];
+        GAS float *rew_l[TPL];
+#pragma unroll
+        for (int m = 0; m < TPL; ++m) {
+            obs_l[m] = obs_p + (uint32_t)((l + m * LANES) * C * W);
+            rew_l[m] = obs_only ? nullptr : rew_p + (uint32_t)(l + m * LANES);
+        }
         auto store_obs = [&](int m) __attribute__((always_inline)) {
-            GAS uint32_t *oa = obs_p + (uint32_t)((l + m * LANES) * C * W);
+            GAS uint32_t *oa = obs_l[m];
             store_words<W>(oa, wall[m]);
             store_words<W>(oa + W, team[m]);
             store_words<W>(oa + 2 * W, opp[m]);
@@ -702,9 +719,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 for (int i = 0; i < NMAX; ++i) {
 #pragma unroll
                     for (int jj = i + 1; jj < NMAX; ++jj, ++pi) {
-                        const uint32_t dx = (uint32_t)((pp[i] & 0xff) - (pp[jj] & 0xff) + R);
-                        const uint32_t dy = (uint32_t)((pp[i] >> 8) - (pp[jj] >> 8) + R);
-                        const bool in = (dx > dy ? dx : dy) < (uint32_t)D;
+                        // u = (dy + R) << 8 | (dx + R) when both differences are
+                        // within R; otherwise a byte of u is at least D
+                        const uint32_t u = (uint32_t)(pp[i] - pp[jj]) + (uint32_t)(R * 256 + R);
+                        const uint32_t lo = u & 0xffu, hi = u >> 8;
+                        const bool in = (lo > hi ? lo : hi) < (uint32_t)D;
                         near |= in ? 1u << pi : 0u;
                         seen_h |= in ? pair_hb[pi] : 0u;
                     }
@@ -735,7 +754,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             for (int m = 0; m < TPL; ++m) {
                 if (mine_live[m]) {
                     store_obs(m);
-                    rew_p[l + m * LANES] = rv[m];
+                    *rew_l[m] = rv[m];
                     if (m == 0) *done_p = (uint8_t)d;
                 }
             }
@@ -764,8 +783,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field<R, W>(wall[m]); });
             }
             steps += 1u;
-            obs_p += J.obs_stride;
-            rew_p += J.agent_stride;
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) {
+                obs_l[m] += J.obs_stride;
+                rew_l[m] += J.agent_stride;
+            }
             done_p += J.env_stride;
         };
 

@@ -711,6 +711,17 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             // ---- 3 detection at the post-move positions, and the channels
             all_masks<R, W, NMAX, TPL, EX>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                            wall, outm, team, opp, cnt);
+            // The role channels feed only the (predicated) stores, so the
+            // compiler would compute them inside the store region; using them
+            // here keeps them in the step's main block, where they fill the
+            // wait for the window rows' LDS reads. Measured faster for every
+            // variant but the unrolled one with two-word windows.
+            if constexpr (!UNROLL || W == 1) {
+#pragma unroll
+                for (int m = 0; m < TPL; ++m)
+#pragma unroll
+                    for (int i = 0; i < W; ++i) asm volatile("" ::"v"(team[m][i]), "v"(opp[m][i]));
+            }
             float rv[TPL];
             if constexpr (PAIRS) {
                 uint32_t near = 0u, seen_h = 0u;

@@ -39,6 +39,7 @@
 #define OR_COLLIDE 1u
 #define OR_CAPTURE 2u
 #define OR_DESYNC 4u
+#define OR_OCCLUDE 8u
 
 #define OR_STREAM_ACTION 0u
 #define OR_STREAM_SPAWN 1u
@@ -134,6 +135,75 @@ static int or_in_bounds(int x, int y, int W, int H)
     return x >= 0 && x < W && y >= 0 && y < H;
 }
 
+/* ----------------------------------------------------------- line of sight */
+
+/* Does the open segment from the centre of cell (0,0) to the centre of cell
+ * (dx,dy) cross the interior of the unit square of cell (ex,ey)? Cells are
+ * unit squares centred on integer points. The segment is P(t) = t*(dx,dy),
+ * 0 < t < 1; the open square needs |x - ex| < 1/2 and |y - ey| < 1/2. Each
+ * coordinate gives an open interval of t (all of t when the direction is 0
+ * and the centre lies on the line, none when it does not); the segment
+ * crosses the square iff the intersection of these intervals with (0,1) is
+ * not empty. Interval ends are fractions num/den with den > 0, compared by
+ * cross-multiplication, so the test is exact. A segment through a corner of
+ * the square, or along its edge, does not cross it. */
+typedef struct { int64_t num, den; } or_frac;
+
+static int or_frac_lt(or_frac a, or_frac b) { return a.num * b.den < b.num * a.den; }
+
+static int or_axis_interval(int d, int e, or_frac *lo, or_frac *hi)
+{
+    if (d == 0) return e == 0; /* |0 - e| < 1/2 for every t, or never */
+    if (d > 0) {
+        lo->num = 2 * e - 1; lo->den = 2 * d;  /* t > (2e-1)/(2d) */
+        hi->num = 2 * e + 1; hi->den = 2 * d;  /* t < (2e+1)/(2d) */
+    } else {
+        lo->num = -(2 * e + 1); lo->den = -2 * d; /* dividing by d < 0 swaps the ends */
+        hi->num = -(2 * e - 1); hi->den = -2 * d;
+    }
+    return 1;
+}
+
+static int or_segment_crosses(int dx, int dy, int ex, int ey)
+{
+    or_frac lo = { 0, 1 }, hi = { 1, 1 }, a, b;
+    if (!or_axis_interval(dx, ex, &a, &b)) return 0;
+    if (dx != 0) {
+        if (or_frac_lt(lo, a)) lo = a;
+        if (or_frac_lt(b, hi)) hi = b;
+    }
+    if (!or_axis_interval(dy, ey, &a, &b)) return 0;
+    if (dy != 0) {
+        if (or_frac_lt(lo, a)) lo = a;
+        if (or_frac_lt(b, hi)) hi = b;
+    }
+    return or_frac_lt(lo, hi);
+}
+
+/* Line of sight (reading of the observation function of Sec. 3.1, a
+ * deterministic line-of-sight projection, reduced to the grid; enabled per
+ * env by OR_OCCLUDE): cell (cx,cy) is visible from the agent's cell (ax,ay)
+ * iff no blocking cell -- a wall, or a cell outside the map -- other than
+ * the two end cells has its interior crossed by the open segment joining
+ * their centres. Only cells of the bounding box of the two cells can be
+ * crossed. */
+static int or_visible(const int32_t *sp, const uint8_t *walls, int ax, int ay, int cx, int cy)
+{
+    int H = sp[SP_H], W = sp[SP_W];
+    int dx = cx - ax, dy = cy - ay;
+    int x0 = dx < 0 ? dx : 0, x1 = dx < 0 ? 0 : dx;
+    int y0 = dy < 0 ? dy : 0, y1 = dy < 0 ? 0 : dy;
+    for (int ey = y0; ey <= y1; ++ey) {
+        for (int ex = x0; ex <= x1; ++ex) {
+            if ((ex == 0 && ey == 0) || (ex == dx && ey == dy)) continue;
+            int bx = ax + ex, by = ay + ey;
+            int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx];
+            if (blocking && or_segment_crosses(dx, dy, ex, ey)) return 0;
+        }
+    }
+    return 1;
+}
+
 /* Agent spawn for episode `e` (reading: agents are placed one after another
  * in index order; agent i tries up to 64 uniformly drawn cells and takes the
  * first that is neither a wall nor held by an agent < i; if all 64 draws fail
@@ -172,11 +242,13 @@ static void or_spawn(const int32_t *sp, const uint8_t *walls, uint8_t *px, uint8
  * k = (dy+r)*(2r+1) + (dx+r), packed LSB-first into ceil((2r+1)^2/32) words
  * per channel. Channels: 0 blocking tile or outside the map, 1 teammate
  * (another agent of the same role), 2 opponent, 3 (only when C = 4) outside
- * the map. Layout [agent][channel][word]. */
+ * the map. Layout [agent][channel][word]. With OR_OCCLUDE, a window cell not
+ * visible from the agent (or_visible) reads 0 in every channel. */
 static void or_observe(const int32_t *sp, const uint8_t *walls, const uint8_t *px,
                        const uint8_t *py, uint32_t *obs)
 {
     int H = sp[SP_H], W = sp[SP_W], n = sp[SP_N], S = sp[SP_S], r = sp[SP_R], C = sp[SP_C];
+    int occlude = ((uint32_t)sp[SP_FLAGS] & OR_OCCLUDE) != 0;
     int d = 2 * r + 1, w = or_words(r);
     memset(obs, 0, sizeof(uint32_t) * (size_t)(n * C * w));
     for (int i = 0; i < n; ++i) {
@@ -185,6 +257,7 @@ static void or_observe(const int32_t *sp, const uint8_t *walls, const uint8_t *p
             for (int dx = -r; dx <= r; ++dx) {
                 int k = (dy + r) * d + (dx + r);
                 int cx = px[i] + dx, cy = py[i] + dy;
+                if (occlude && !or_visible(sp, walls, px[i], py[i], cx, cy)) continue;
                 int inb = or_in_bounds(cx, cy, W, H);
                 uint32_t bit = 1u << (k & 31);
                 int word = k >> 5;
@@ -264,7 +337,8 @@ static const int OR_DY[5] = { 0, -1, 1, 0, 0 };
  *   2 moves in agent-index order; a move is rejected if it leaves the map,
  *     enters a blocking tile, or (collisions on) enters a cell held by any
  *     other agent at that moment (agents < i already moved, agents > i not);
- *   3 detection: seeker i sees hider h iff their Chebyshev distance is <= r;
+ *   3 detection: seeker i sees hider h iff their Chebyshev distance is <= r
+ *     (and, with OR_OCCLUDE, h's cell is visible from i's, or_visible);
  *     seeker reward = hiders seen, hider reward = -(seekers seeing it)
  *     (zero-sum, Sec. 3 "zero-sum adversarial control"); seen hiders get the
  *     latched Found flag;
@@ -321,7 +395,8 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
             if (ddx < 0) ddx = -ddx;
             if (ddy < 0) ddy = -ddy;
             int cheb = ddx > ddy ? ddx : ddy;
-            if (cheb <= r) {
+            int vis = !(flags & OR_OCCLUDE) || or_visible(sp, walls, px[i], py[i], px[h], py[h]);
+            if (cheb <= r && vis) {
                 count[i] += 1;
                 count[h] += 1;
                 b->found[e] |= 1u << h;
@@ -382,6 +457,12 @@ void or_philox_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_
 {
     uint32_t ctr[4] = { c0, c1, c2, c3 }, key[2] = { k0, k1 };
     or_philox4x32_10(ctr, key, out);
+}
+
+/* Line of sight of one cell pair, exported so the rule can be tested alone. */
+int or_los(const int32_t *sp, const uint8_t *walls, int ax, int ay, int cx, int cy)
+{
+    return or_visible(sp, walls, ax, ay, cx, cy);
 }
 
 /* Plain spawn of one env, exported so the spawn rule can be tested alone. */

@@ -79,6 +79,8 @@ def _bind(path: str):
     L.or_spawn_env.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                ctypes.c_uint32]
+    L.or_los.restype = ctypes.c_int
+    L.or_los.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 4
     return L
 
 
@@ -217,3 +219,12 @@ def spawn(spec: dict, walls: np.ndarray, seed: int, env: int, episode: int):
     lib().or_spawn_env(sp.ctypes.data, walls.ctypes.data, px.ctypes.data, py.ctypes.data,
                        ctypes.c_uint64(seed), int(env), int(episode))
     return px, py
+
+
+def los(spec: dict, walls: np.ndarray, ax: int, ay: int, cx: int, cy: int) -> bool:
+    """Line of sight from cell (ax, ay) to cell (cx, cy) under the oracle's
+    rule (cells may lie outside the map; exported for the rule's pins)."""
+    sp = spec_table([spec])[0].copy()
+    walls = np.ascontiguousarray(walls, dtype=np.uint8)
+    return bool(lib().or_los(sp.ctypes.data, walls.ctypes.data, int(ax), int(ay), int(cx),
+                             int(cy)))

@@ -9,9 +9,15 @@ Rules restated (see the step rules documented with the library):
   moves, agent-index order: a move to target T is taken iff T is inside the
     map, not a blocking tile, and (collisions on) no other agent stands on T at
     that moment; out-of-range action codes are stay;
-  detection: Chebyshev distance <= r between seeker and hider;
+  detection: Chebyshev distance <= r between seeker and hider (and, with the
+    occlusion flag 8, the hider's cell visible from the seeker's);
   done: terminated (capture rule, >= 1 hider, all hiders found) | truncated << 1;
-  observation: window rows dy = -r..r, columns dx = -r..r, bit (dy+r)(2r+1)+(dx+r).
+  observation: window rows dy = -r..r, columns dx = -r..r, bit (dy+r)(2r+1)+(dx+r);
+    with the occlusion flag, invisible window cells read 0 in every channel.
+  visibility: a window cell is hidden iff the open segment between the two
+    cell centres passes through the inside of a blocking cell (wall or outside
+    the map) other than the two end cells. Here found by sampling the segment
+    (crossed_cells), not by the interval test of the oracle.
 """
 from __future__ import annotations
 
@@ -21,6 +27,45 @@ import numpy as np
 
 DX = np.array([0, 0, 0, 1, -1])
 DY = np.array([0, -1, 1, 0, 0])
+OCCLUDE = 8
+
+
+def crossed_cells(dx, dy, N=48):
+    """Cells (ex, ey), other than (0, 0) and (dx, dy), whose open unit square
+    holds a point of the open segment from (0, 0) to (dx, dy), found by
+    sampling t = (2k+1)/(2N), k < N, in exact integer arithmetic (the point is
+    ((2k+1) dx, (2k+1) dy) / 2N). Exactness: whether the segment is inside a
+    cell's open square is decided by open t-intervals whose ends are 0, 1 or
+    (2e +- 1)/(2|d|) for d = dx or dy; for |d| <= 4 every end is a multiple of
+    1/24, so a non-empty intersection contains an odd multiple of 1/48, i.e.
+    a sample when N is a multiple of 24."""
+    out = set()
+    for k in range(N):
+        X, Y = (2 * k + 1) * dx, (2 * k + 1) * dy
+        for ey in range(min(0, dy), max(0, dy) + 1):
+            for ex in range(min(0, dx), max(0, dx) + 1):
+                if (ex, ey) in ((0, 0), (dx, dy)):
+                    continue
+                if abs(X - 2 * N * ex) < N and abs(Y - 2 * N * ey) < N:
+                    out.add((ex, ey))
+    return sorted(out)
+
+
+def visible_window(spec, walls, x, y):
+    """[B][D][D] bool: window cell (dy, dx) of the agent at (x, y) visible."""
+    H, W, r = spec["H"], spec["W"], spec["r"]
+    D = 2 * r + 1
+    B = x.shape[0]
+    P = r
+    blocking = np.ones((B, H + 2 * P, W + 2 * P), bool)
+    blocking[:, P:P + H, P:P + W] = walls.reshape(B, H, W) == 1
+    rows = np.arange(B)
+    vis = np.ones((B, D, D), bool)
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            for ex, ey in crossed_cells(dx, dy):
+                vis[:, dy + r, dx + r] &= ~blocking[rows, y + ey + P, x + ex + P]
+    return vis
 
 
 def _state(B, H, W, n):
@@ -129,14 +174,20 @@ def expected_moves(spec, st, acts):
     return x, y
 
 
-def expected_detection(spec, x, y):
+def expected_detection(spec, x, y, walls=None):
     n, S, r = spec["n"], spec["S"], spec["r"]
     B = x.shape[0]
     cnt = np.zeros((B, n), np.int64)
     found = np.zeros(B, np.uint32)
+    occl = bool(spec["flags"] & OCCLUDE)
     for i in range(S):
+        vis = visible_window(spec, walls, x[:, i], y[:, i]) if occl else None
         for h in range(S, n):
             seen = np.maximum(np.abs(x[:, i] - x[:, h]), np.abs(y[:, i] - y[:, h])) <= r
+            if occl:
+                ddy = np.clip(y[:, h] - y[:, i] + r, 0, 2 * r)
+                ddx = np.clip(x[:, h] - x[:, i] + r, 0, 2 * r)
+                seen &= vis[np.arange(B), ddy, ddx]
             cnt[:, i] += seen
             cnt[:, h] += seen
             found |= (seen.astype(np.uint32) << np.uint32(h))
@@ -174,6 +225,9 @@ def expected_obs(spec, walls, x, y):
         ch1 = (same > 0) & inb
         ch2 = (occ_role[1 - int(role[i])][bb, wy, wx] > 0) & inb
         chans = [ch0, ch1, ch2] + ([~inb] if C == 4 else [])
+        if spec["flags"] & OCCLUDE:
+            vis = visible_window(spec, walls, x[:, i], y[:, i])
+            chans = [m & vis for m in chans]
         for c, m in enumerate(chans):
             flat = m.reshape(B, D * D).astype(np.uint64)
             for k in range(D * D):
@@ -188,7 +242,7 @@ def check_step(spec, st, acts, obs, rew, done, new_state):
     H, W, n, S, L = (spec[k] for k in ("H", "W", "n", "S", "L"))
     B = st["pos_x"].shape[0]
     x, y = expected_moves(spec, st, acts)
-    ex_rew, seen = expected_detection(spec, x, y)
+    ex_rew, seen = expected_detection(spec, x, y, st["walls"])
     np.testing.assert_array_equal(rew.reshape(B, n), ex_rew)
     assert not np.signbit(rew[rew == 0]).any()
     found = st["found"] | seen

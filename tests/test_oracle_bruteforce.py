@@ -27,6 +27,12 @@ FAMILIES = {
                                                                flags=0, seed=6),
     "three_agents_open": lambda: bf.case_three_agents(r=2, C=3, flags=1),
     "three_agents_capture": lambda: bf.case_three_agents(r=1, C=4, flags=3, S=1),
+    "one_agent_occluded_r3": lambda: bf.case_one_agent(r=3, C=4, flags=8 | 3,
+                                                       subsample=100_000, seed=7),
+    "seeker_hider_occluded_r3": lambda: bf.case_seeker_hider(n_patterns=96, r=3, C=4,
+                                                             flags=8 | 1, seed=8),
+    "seeker_hider_occluded_capture": lambda: bf.case_seeker_hider(n_patterns=64, r=2, C=3,
+                                                                  flags=8 | 3, seed=9),
 }
 
 

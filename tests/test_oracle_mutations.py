@@ -35,6 +35,17 @@ MUTATIONS = {
     "obs_before_reset": ("    /* 5 auto-reset */\n    if (d) {",
                          "    or_observe(sp, walls, px, py, obs);\n    if (0) {"),
     "opponent_as_teammate": ("if (or_is_seeker(j, S) == or_is_seeker(i, S))", "if (1)"),
+    "los_corner_touch_blocks": ("return a.num * b.den < b.num * a.den;",
+                                "return a.num * b.den <= b.num * a.den;"),
+    "los_target_blocks_itself": ("if ((ex == 0 && ey == 0) || (ex == dx && ey == dy)) continue;",
+                                 "if (ex == 0 && ey == 0) continue;"),
+    "los_negative_direction_interval": ("lo->num = -(2 * e + 1); lo->den = -2 * d;",
+                                        "lo->num = -(2 * e - 1); lo->den = -2 * d;"),
+    "los_outside_not_blocking": ("int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx];",
+                                 "int blocking = or_in_bounds(bx, by, W, H) && walls[by * W + bx];"),
+    "detection_ignores_los": (
+        "int vis = !(flags & OR_OCCLUDE) || or_visible(sp, walls, px[i], py[i], px[h], py[h]);",
+        "int vis = 1;"),
 }
 
 
@@ -61,7 +72,9 @@ def run_pins(libpath, rocrand_philox):
         fams = [bf.case_one_agent(r=1, C=4, subsample=30_000, seed=1),
                 bf.case_seeker_hider(n_patterns=12, flags=1),
                 bf.case_seeker_hider(n_patterns=12, flags=3, seed=2),
-                bf.case_three_agents(r=1, C=4, flags=3, S=1)]
+                bf.case_three_agents(r=1, C=4, flags=3, S=1),
+                bf.case_one_agent(r=3, C=4, flags=8 | 3, subsample=20_000, seed=7),
+                bf.case_seeker_hider(n_patterns=12, r=3, C=4, flags=8 | 1, seed=8)]
         for spec, st, acts in fams:
             B = st["pos_x"].shape[0]
             table = np.tile(np.array([[spec[f] for f in o.SPEC_FIELDS]], np.int32), (B, 1))

@@ -51,6 +51,13 @@ extern "C" {
 #define HASE_COLLIDE 1u      /* a move into a cell held by another agent is rejected */
 #define HASE_CAPTURE_ENDS 2u /* the episode terminates once every hider was found */
 #define HASE_DESYNC 4u       /* first episode starts with t0 ~ U{0..L-1} elapsed */
+/* line of sight (Sec. 3.1, observation function: a deterministic line-of-sight
+ * projection): a window cell is hidden when the open segment between the
+ * centres of the agent's cell and that cell passes through the inside of a
+ * blocking cell (a wall or outside the map) other than the two end cells;
+ * hidden cells read 0 in every channel and a seeker sees a hider only if the
+ * hider's cell is visible */
+#define HASE_OCCLUDE 8u
 
 /* step modes */
 #define HASE_STEP_PERSISTENT 0u  /* all n_steps in one launch per tile variant (graph-replayed) */

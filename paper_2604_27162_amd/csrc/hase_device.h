@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "hase_internal.h"
 
@@ -278,7 +279,7 @@ constexpr uint64_t MOVE_TABLE = 0x101ull | (0x001ull << 12) | (0x201ull << 24) |
 // every other agent by index. Returns the number of other-role agents in the
 // window (Chebyshev distance <= R).
 template <int R, int W, int NMAX, bool EXACT>
-__device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
+__device__ __forceinline__ int agent_masks_raw(const uint32_t *slot, int H, int Wd,
                                            const int (&pp)[NMAX], int a, int pa, int n, int S,
                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
                                            uint32_t (&team)[W], uint32_t (&opp)[W])
@@ -403,7 +404,162 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
     }
 }
 
-template <int R, int W, int NMAX, int TPL, bool EXACT>
+// ------------------------------------------------------------ line of sight
+
+// Does the open segment from the centre of window cell (0,0) to the centre of
+// (dx,dy) pass through the inside of the unit square of cell (ex,ey)? Both
+// are open convex sets, so they meet iff no separating axis exists among the
+// square's edge normals (x, y) and the segment's normal (-dy, dx): along x and
+// y their open projections must overlap, along the normal the square's corners
+// must lie strictly on both sides of the segment's line. Doubled coordinates
+// keep every quantity an integer.
+constexpr bool seg_cuts_cell(int dx, int dy, int ex, int ey)
+{
+    auto overlap = [](int a0, int a1, int b0, int b1) {
+        return (a0 > b0 ? a0 : b0) < (a1 < b1 ? a1 : b1);
+    };
+    const int lx = dx < 0 ? dx : 0, hx = dx < 0 ? 0 : dx;
+    const int ly = dy < 0 ? dy : 0, hy = dy < 0 ? 0 : dy;
+    if (dx == 0 ? ex != 0 : !overlap(2 * lx, 2 * hx, 2 * ex - 1, 2 * ex + 1)) return false;
+    if (dy == 0 ? ey != 0 : !overlap(2 * ly, 2 * hy, 2 * ey - 1, 2 * ey + 1)) return false;
+    int fmin = 0x7fffffff, fmax = -0x7fffffff;
+    for (int sx = -1; sx <= 1; sx += 2) {
+        for (int sy = -1; sy <= 1; sy += 2) {
+            const int f = -dy * (2 * ex + sx) + dx * (2 * ey + sy);
+            fmin = f < fmin ? f : fmin;
+            fmax = f > fmax ? f : fmax;
+        }
+    }
+    return fmin < 0 && 0 < fmax;
+}
+
+// Shadow table of radius R: for each cell b within Chebyshev distance R - 1
+// of the centre (only those can lie strictly between the centre and a window
+// cell), its window bit and the window cells whose segment from the centre
+// passes through b's inside (bit k = (dy + R)(2R + 1) + dx + R).
+template <int R>
+struct LosTable {
+    static constexpr int D = 2 * R + 1;
+    static constexpr int W = (D * D + 31) / 32;
+    static constexpr int NB = (2 * R - 1) * (2 * R - 1) - 1;
+    int bit[NB > 0 ? NB : 1];
+    uint32_t shadow[NB > 0 ? NB : 1][W];
+    constexpr LosTable() : bit(), shadow()
+    {
+        int i = 0;
+        for (int ey = -(R - 1); ey <= R - 1; ++ey) {
+            for (int ex = -(R - 1); ex <= R - 1; ++ex) {
+                if (ex == 0 && ey == 0) continue;
+                bit[i] = (ey + R) * D + ex + R;
+                for (int w = 0; w < W; ++w) shadow[i][w] = 0u;
+                for (int dy = -R; dy <= R; ++dy) {
+                    for (int dx = -R; dx <= R; ++dx) {
+                        if (dx == ex && dy == ey) continue;
+                        if (seg_cuts_cell(dx, dy, ex, ey)) {
+                            const int k = (dy + R) * D + dx + R;
+                            shadow[i][k >> 5] |= 1u << (k & 31);
+                        }
+                    }
+                }
+                ++i;
+            }
+        }
+    }
+};
+
+template <int R>
+inline constexpr LosTable<R> LOS_TABLE{};
+
+// occ |= shadow of blocker I when the window shows a blocking cell there. The
+// table entries are constexpr locals (template indices only), so they are
+// immediate constants of the kernel and zero words cost nothing.
+template <int R, int W, int I, int WI>
+__device__ __forceinline__ void los_word(uint32_t (&occ)[W], uint32_t m)
+{
+    constexpr uint32_t sh = LOS_TABLE<R>.shadow[I][WI];
+    if constexpr (sh != 0u) occ[WI] |= sh & m;
+}
+
+template <int R, int W, int I, int... WI>
+__device__ __forceinline__ void los_one(const uint32_t (&wall)[W], uint32_t (&occ)[W],
+                                        std::integer_sequence<int, WI...>)
+{
+    constexpr int b = LOS_TABLE<R>.bit[I];
+    const uint32_t m = 0u - ((wall[b >> 5] >> (b & 31)) & 1u);
+    (los_word<R, W, I, WI>(occ, m), ...);
+}
+
+template <int R, int W, int... I>
+__device__ __forceinline__ void los_all(const uint32_t (&wall)[W], uint32_t (&occ)[W],
+                                        std::integer_sequence<int, I...>)
+{
+    (los_one<R, W, I>(wall, occ, std::make_integer_sequence<int, W>{}), ...);
+}
+
+// Visible window cells of an agent from its wall|outside window: every cell
+// not in the shadow of a blocking cell.
+template <int R, int W>
+__device__ __forceinline__ void los_visible(const uint32_t (&wall)[W], uint32_t (&vis)[W])
+{
+    uint32_t occ[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) occ[w] = 0u;
+    if constexpr (LosTable<R>::NB > 0)
+        los_all<R, W>(wall, occ, std::make_integer_sequence<int, LosTable<R>::NB>{});
+#pragma unroll
+    for (int w = 0; w < W; ++w) vis[w] = ~occ[w];
+}
+
+// Channels of one agent (agent_masks_raw), and with line of sight (OCC)
+// every channel restricted to the visible cells and the opponent count
+// restricted to visible opponents.
+template <int R, int W, int NMAX, bool EXACT, bool OCC>
+__device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
+                                           const int (&pp)[NMAX], int a, int pa, int n, int S,
+                                           bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
+                                           uint32_t (&team)[W], uint32_t (&opp)[W])
+{
+    int cnt = agent_masks_raw<R, W, NMAX, EXACT>(slot, H, Wd, pp, a, pa, n, S, want_out, wall,
+                                                 outm, team, opp);
+    if constexpr (OCC) {
+        uint32_t vis[W];
+        los_visible<R, W>(wall, vis);
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            wall[i] &= vis[i];
+            outm[i] &= vis[i];
+            team[i] &= vis[i];
+            opp[i] &= vis[i];
+        }
+        if constexpr (!EXACT) {
+            // distinct cells: one opponent per opponent bit
+            cnt = 0;
+#pragma unroll
+            for (int i = 0; i < W; ++i) cnt += __builtin_popcount(opp[i]);
+        } else {
+            // agents may share cells: count visible opponents one by one
+            constexpr int D = 2 * R + 1;
+            const int ax = pa & 0xff, ay = pa >> 8;
+            const bool sa = a < S;
+            cnt = 0;
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j) {
+                const int dx = (pp[j] & 0xff) - ax + R;
+                const int dy = (pp[j] >> 8) - ay + R;
+                const bool in = j < n && j != a && (uint32_t)dx < (uint32_t)D &&
+                                (uint32_t)dy < (uint32_t)D && ((j < S) != sa);
+                const int kk = in ? dy * D + dx : 0;
+                uint32_t vw = vis[0];
+#pragma unroll
+                for (int i = 1; i < W; ++i) vw = (kk >> 5) == i ? vis[i] : vw;
+                cnt += (in && ((vw >> (kk & 31)) & 1u)) ? 1 : 0;
+            }
+        }
+    }
+    return cnt;
+}
+
+template <int R, int W, int NMAX, int TPL, bool EXACT, bool OCC>
 __device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
                                           const int (&pp)[NMAX], int l, int lanes,
                                           const int (&mine)[TPL], int n, int S, bool want_out,
@@ -413,7 +569,7 @@ __device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
 {
 #pragma unroll
     for (int m = 0; m < TPL; ++m)
-        cnt[m] = agent_masks<R, W, NMAX, EXACT>(slot, H, Wd, pp, l + m * lanes, mine[m], n, S,
+        cnt[m] = agent_masks<R, W, NMAX, EXACT, OCC>(slot, H, Wd, pp, l + m * lanes, mine[m], n, S,
                                                 want_out, wall[m], outm[m], team[m], opp[m]);
 }
 
@@ -458,7 +614,7 @@ __device__ __forceinline__ uint32_t gather_blocked(int l, F field)
 // the current state only. UNROLL unrolls the step loop over each action
 // window (single-variant launches; the mixed kernel keeps one copy per
 // variant to bound its code size).
-template <int LANES, int NMAX, int R, bool UNROLL>
+template <int LANES, int NMAX, int R, bool UNROLL, bool OCC_OK>
 __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, uint32_t K,
                                           uint32_t step_base, uint32_t slot_words, uint32_t *lds)
 {
@@ -606,8 +762,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // The step loop, instantiated for channels computed assuming distinct
     // agent cells (collisions on) and for the exact per-agent test; the choice
     // is made once per env, outside the loop.
-    auto run = [&](auto exact_tag) {
+    auto run = [&](auto exact_tag, auto occ_tag) {
         constexpr bool EX = decltype(exact_tag)::value;
+        // line of sight: channels and counts restricted to visible cells;
+        // detection then goes through the counts (the pairwise test knows no
+        // walls), and the loop is not unrolled (bounded code size)
+        constexpr bool OC = decltype(occ_tag)::value;
+        constexpr bool USE_PAIRS = PAIRS && !OC;
         uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W];
         int cnt[TPL];
 
@@ -628,7 +789,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         };
 
         if (obs_only) {
-            all_masks<R, W, NMAX, TPL, EX>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
+            all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                            wall, outm, team, opp, cnt);
 #pragma unroll
             for (int m = 0; m < TPL; ++m)
@@ -709,7 +870,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
             // ---- 3 detection at the post-move positions, and the channels
-            all_masks<R, W, NMAX, TPL, EX>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
+            all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                            wall, outm, team, opp, cnt);
             // The role channels feed only the (predicated) stores, so the
             // compiler would compute them inside the store region; using them
@@ -723,7 +884,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     for (int i = 0; i < W; ++i) asm volatile("" ::"v"(team[m][i]), "v"(opp[m][i]));
             }
             float rv[TPL];
-            if constexpr (PAIRS) {
+            if constexpr (USE_PAIRS) {
                 uint32_t near = 0u, seen_h = 0u;
                 int pi = 0;
 #pragma unroll
@@ -785,7 +946,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 #pragma unroll
                 for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
                 own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-                all_masks<R, W, NMAX, TPL, EX>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
+                all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
                                                wall, outm, team, opp, cnt);
 #pragma unroll
                 for (int m = 0; m < TPL; ++m)
@@ -811,7 +972,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 
         if constexpr (DPP_WINDOW) {
             // lane l draws the block of step steps + l; a window covers LANES steps
-            if constexpr (UNROLL) {
+            if constexpr (UNROLL && !OC) {
                 uint32_t k = 0;
                 for (; k + LANES <= nsteps; k += LANES) {
                     const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
@@ -857,10 +1018,23 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             }
         }
     };
-    if (collide)
-        run(std::false_type{});
-    else
-        run(std::true_type{});
+    // Line of sight is compiled into the mixed kernel only (the host routes
+    // every tile with an occluding env there), with the exact per-agent
+    // channels, which are right whether or not agents may share a cell; the
+    // distinct-cell shortcut is kept for the plain loop.
+    bool occ_done = false;
+    if constexpr (OCC_OK) {
+        if ((flags & 8u) != 0u) {
+            run(std::true_type{}, std::true_type{});
+            occ_done = true;
+        }
+    }
+    if (!occ_done) {
+        if (collide)
+            run(std::false_type{}, std::false_type{});
+        else
+            run(std::true_type{}, std::false_type{});
+    }
 
     // write back the state
     if (active && !obs_only) {
@@ -890,7 +1064,7 @@ __global__ __launch_bounds__(64) void step_kernel(const Tile *__restrict__ tiles
     if (blockIdx.x >= n_tiles) return;
     const Tile tile = tiles[blockIdx.x];
     const JobDesc J = jobs ? jobs[tile.job] : job0;
-    step_tile<LANES, NMAX, R, true>(tile, J, K, step_base, slot_words, lds);
+    step_tile<LANES, NMAX, R, true, false>(tile, J, K, step_base, slot_words, lds);
 }
 
 // Variant code of a tile: agent-count bucket * 4 + radius - 1.
@@ -903,10 +1077,10 @@ __device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobD
     constexpr int NMAX = BUCKET_NMAX[B];
     if constexpr ((NMAX + LANES - 1) / LANES <= 4) {
         switch (r) {
-        case 1: step_tile<LANES, NMAX, 1, false>(tile, J, K, step_base, slot_words, lds); break;
-        case 2: step_tile<LANES, NMAX, 2, false>(tile, J, K, step_base, slot_words, lds); break;
-        case 3: step_tile<LANES, NMAX, 3, false>(tile, J, K, step_base, slot_words, lds); break;
-        default: step_tile<LANES, NMAX, 4, false>(tile, J, K, step_base, slot_words, lds); break;
+        case 1: step_tile<LANES, NMAX, 1, false, true>(tile, J, K, step_base, slot_words, lds); break;
+        case 2: step_tile<LANES, NMAX, 2, false, true>(tile, J, K, step_base, slot_words, lds); break;
+        case 3: step_tile<LANES, NMAX, 3, false, true>(tile, J, K, step_base, slot_words, lds); break;
+        default: step_tile<LANES, NMAX, 4, false, true>(tile, J, K, step_base, slot_words, lds); break;
         }
     }
 }

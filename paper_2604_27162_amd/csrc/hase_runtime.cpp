@@ -80,7 +80,7 @@ int check_spec(const hase_env_spec &s, uint32_t idx)
     if (s.n_channels != 3 && s.n_channels != 4)
         return fail(HASE_EINVAL, "spec %u: n_channels must be 3 or 4", idx);
     if (s.wall_pct > 99) return fail(HASE_EINVAL, "spec %u: wall_pct must be <= 99", idx);
-    if (s.flags & ~7u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
+    if (s.flags & ~15u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
     if (s.episode_len < 1) return fail(HASE_EINVAL, "spec %u: episode_len must be >= 1", idx);
     return HASE_OK;
 }
@@ -168,7 +168,9 @@ int make_plan(const hase_batch_desc *d, Plan &p)
 // (mixed) every variant sharing `lanes`, over contiguous tiles.
 struct Variant {
     int lanes = 0, nmax = 0, r = 0;
-    bool mixed = false;
+    // mixed: the per-tile variant switch; also required when any env of the
+    // group sets line of sight (occ), which only that kernel implements
+    bool mixed = false, occ = false;
     uint32_t tile0 = 0, n_tiles = 0, slot_words = 0;
 };
 
@@ -247,8 +249,12 @@ int build_tiles(hase_batch *b)
                     if (bucket_of(p.specs[e].n_agents) == bk && p.specs[e].view_radius == r)
                         ids.push_back(e);
                 if (ids.empty()) continue;
+                // occluding envs together (a wave runs one loop body per flag
+                // present), then by agent count and area
                 std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
                     const hase_env_spec &x = p.specs[a], &y = p.specs[c];
+                    const bool ox = (x.flags & HASE_OCCLUDE) != 0, oy = (y.flags & HASE_OCCLUDE) != 0;
+                    if (ox != oy) return ox;
                     if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
                     return x.height * x.width > y.height * y.width;
                 });
@@ -256,6 +262,7 @@ int build_tiles(hase_batch *b)
                 const uint32_t base = (uint32_t)perm.size();
                 for (uint32_t e : ids) {
                     perm.push_back(e);
+                    if (p.specs[e].flags & HASE_OCCLUDE) grp.occ = true;
                     grp.slot_words = std::max(grp.slot_words, (uint32_t)lds_board_words(p.specs[e].height));
                 }
                 for (uint32_t i = 0; i < ids.size(); i += E) {
@@ -272,7 +279,7 @@ int build_tiles(hase_batch *b)
             }
         }
         if (n_var == 0) continue;
-        grp.mixed = n_var > 1;
+        grp.mixed = n_var > 1 || grp.occ;
         grp.n_tiles = (uint32_t)tiles.size() - grp.tile0;
         const size_t lds_bytes = (size_t)(64u / L) * (grp.slot_words + MAX_AGENTS) * 4;
         if (lds_bytes > 65536)
@@ -861,6 +868,7 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
                     tiles.push_back(tl);
                 }
                 g.slot = std::max(g.slot, v.slot_words);
+                if (v.occ) g.mixed = true;  // line of sight: mixed kernel only
             }
         }
         g.n_tiles = (uint32_t)tiles.size() - g.tile0;

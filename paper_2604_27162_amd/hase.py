@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhase.so")
 
 OK, EINVAL, ENOMEM, EGRID, EHIP, ESTATE, ENOTREADY = 0, -1, -2, -3, -4, -5, -6
-COLLIDE, CAPTURE_ENDS, DESYNC = 1, 2, 4
+COLLIDE, CAPTURE_ENDS, DESYNC, OCCLUDE = 1, 2, 4, 8
 PERSISTENT, PER_LAUNCH = 0, 1
 N_BUCKETS = 4
 

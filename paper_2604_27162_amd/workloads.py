@@ -23,6 +23,7 @@ import numpy as np
 COLLIDE = 1
 CAPTURE_ENDS = 2
 DESYNC = 4
+OCCLUDE = 8  # line-of-sight occlusion in the windows
 DEFAULT_FLAGS = COLLIDE | CAPTURE_ENDS | DESYNC
 EPISODE_LEN = 256
 

@@ -34,6 +34,8 @@ DESCR = {
     "single1k": "1024 envs, 32x32 grid, 15% iid walls, 1 seeker + 1 hider, 7x7 window, "
                 "3 bit-packed channels, episode 256, counter-generator actions",
     "small": "1024 envs, 16x16 grid, 10% iid walls, 1 seeker + 1 hider, 5x5 window, 3 channels",
+    "los16k": "16384 envs, 32x32 grid, 15% iid walls, 1 seeker + 1 hider, 7x7 window with "
+              "line-of-sight occlusion, 3 bit-packed channels, episode 256",
     "multi10": "4096 envs, 32x32 grid, 15% iid walls, 5 seekers + 5 hiders, 9x9 window, "
                "4 channels, collisions in agent order",
     "uneven8k": "8192 envs: sides {16,32,64} (50/30/20%), 1..10 agents, 5..25% walls, "

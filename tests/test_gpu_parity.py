@@ -250,7 +250,7 @@ def offsets(specs):
 
 
 FULL = [("small", 256, 48), ("single16k", 10000, 24), ("single1k", 10000, 24),
-        ("multi10", 2000, 24), ("uneven8k", 2000, 40)]
+        ("multi10", 2000, 24), ("uneven8k", 2000, 40), ("los16k", 4000, 24)]
 
 
 @pytest.mark.parametrize("name,steps,n_sample", FULL)

@@ -40,6 +40,7 @@
 #define OR_CAPTURE 2u
 #define OR_DESYNC 4u
 #define OR_OCCLUDE 8u
+#define OR_EXPLORE 16u
 
 #define OR_STREAM_ACTION 0u
 #define OR_STREAM_SPAWN 1u
@@ -64,6 +65,9 @@ typedef struct {
     uint32_t *found, *t, *ep, *steps; /* [n_envs] */
     uint64_t *seed;           /* [n_envs] */
     uint32_t *env_id;         /* [n_envs] */
+    const int64_t *disc_off;  /* [n_envs] first discovery-map word of env e */
+    int64_t disc_total;       /* sum of map words over envs */
+    uint32_t *disc;           /* [disc_total] discovery maps (OR_EXPLORE envs) */
 } or_batch;
 
 /* ---------------------------------------------------------------- Philox */
@@ -129,6 +133,10 @@ static int or_words(int r)
 }
 
 static int or_is_seeker(int i, int S) { return i < S; }
+
+/* Discovery map of an OR_EXPLORE env: H rows of ceil(W/32) words, cell (x,y)
+ * at bit x & 31 of word y * ceil(W/32) + x / 32; 0 words for other envs. */
+static int or_map_row_words(int W) { return (W + 31) / 32; }
 
 static int or_in_bounds(int x, int y, int W, int H)
 {
@@ -306,6 +314,8 @@ int or_reset(or_batch *b, uint64_t seed, uint32_t *obs0)
         b->steps[e] = 0;
         b->ep[e] = 0;
         b->found[e] = 0;
+        if ((uint32_t)sp[SP_FLAGS] & OR_EXPLORE)
+            memset(b->disc + b->disc_off[e], 0, sizeof(uint32_t) * (size_t)(H * or_map_row_words(W)));
         or_spawn(sp, walls, px, py, seed, env, 0);
         if (sp[SP_FLAGS] & OR_DESYNC)
             b->t[e] = or_range(or_draw(seed, env, OR_STREAM_DESYNC, 0, 0, 0, 0), (uint32_t)sp[SP_L]);
@@ -344,7 +354,9 @@ static const int OR_DY[5] = { 0, -1, 1, 0, 0 };
  *     latched Found flag;
  *   4 t += 1; terminated = capture rule on, at least one hider, every hider
  *     found; truncated = t >= L; done = terminated | truncated << 1;
- *   5 if done: next episode, t = 0, Found cleared, agents respawned, grid kept;
+ *   3b exploration reward and discovery map (OR_EXPLORE);
+ *   5 if done: next episode, t = 0, Found cleared, agents respawned, grid kept,
+ *     discovery map cleared;
  *   6 step count += 1;
  *   7 observation of the (possibly new) state.
  */
@@ -403,9 +415,43 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
             }
         }
     }
+    /* 3b exploration (reading R27, OR_EXPLORE): each seeker earns 1/128 per
+     * cell of its window -- inside the map and, with OR_OCCLUDE, visible --
+     * that the env's discovery map did not hold before this step (cells new
+     * to several seekers count for each); then every such cell of every
+     * seeker enters the map. The reward is (128 v + new) / 128, exact in
+     * float32. */
+    int fresh[20];
+    for (int i = 0; i < n; ++i) fresh[i] = 0;
+    if (flags & OR_EXPLORE) {
+        uint32_t *map = b->disc + b->disc_off[e];
+        int rw = or_map_row_words(W);
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i < S && i < n; ++i) {
+                for (int dy = -r; dy <= r; ++dy) {
+                    for (int dx = -r; dx <= r; ++dx) {
+                        int cx = px[i] + dx, cy = py[i] + dy;
+                        if (!or_in_bounds(cx, cy, W, H)) continue;
+                        if ((flags & OR_OCCLUDE) && !or_visible(sp, walls, px[i], py[i], cx, cy))
+                            continue;
+                        uint32_t *word = map + (size_t)cy * rw + (cx >> 5);
+                        uint32_t bit = 1u << (cx & 31);
+                        if (pass == 0) {
+                            if (!(*word & bit)) fresh[i] += 1; /* counted against the old map */
+                        } else {
+                            *word |= bit;
+                        }
+                    }
+                }
+            }
+        }
+    }
     for (int i = 0; i < n; ++i) {
         int v = or_is_seeker(i, S) ? count[i] : -count[i];
-        rew[i] = (float)v;
+        if (flags & OR_EXPLORE)
+            rew[i] = (float)(128 * v + fresh[i]) * 0.0078125f;
+        else
+            rew[i] = (float)v;
     }
 
     /* 4 termination / truncation */
@@ -418,11 +464,13 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
     uint8_t d = (uint8_t)((terminated ? 1 : 0) | (truncated ? 2 : 0));
     *done = d;
 
-    /* 5 auto-reset */
+    /* 5 auto-reset (the new episode's discovery map is empty) */
     if (d) {
         b->ep[e] += 1;
         b->t[e] = 0;
         b->found[e] = 0;
+        if (flags & OR_EXPLORE)
+            memset(b->disc + b->disc_off[e], 0, sizeof(uint32_t) * (size_t)(H * or_map_row_words(W)));
         or_spawn(sp, walls, px, py, seed, env, b->ep[e]);
     }
 
@@ -435,10 +483,11 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
 
 /* n_steps consecutive steps of every env. actions is NULL (every action
  * drawn) or [n_steps][agents_total] int8; outputs are obs
- * [n_steps][obs_total] u32, rew [n_steps][agents_total] f32 and done
- * [n_steps][n_envs] u8. */
+ * [n_steps][obs_total] u32, rew [n_steps][agents_total] f32, done
+ * [n_steps][n_envs] u8 and, when maps is not NULL, the discovery maps
+ * [n_steps][disc_total] u32. */
 void or_step(or_batch *b, int n_steps, const int8_t *actions, uint32_t *obs, float *rew,
-             uint8_t *done)
+             uint8_t *done, uint32_t *maps)
 {
     for (int k = 0; k < n_steps; ++k) {
         for (int e = 0; e < b->n_envs; ++e) {
@@ -448,6 +497,10 @@ void or_step(or_batch *b, int n_steps, const int8_t *actions, uint32_t *obs, flo
                         rew + (size_t)k * b->agents_total + b->agent_off[e],
                         done + (size_t)k * b->n_envs + e);
         }
+        /* centralised observation (reading R27): every env's discovery map
+         * after the step, concatenated */
+        if (maps && b->disc_total)
+            memcpy(maps + (size_t)k * b->disc_total, b->disc, sizeof(uint32_t) * (size_t)b->disc_total);
     }
 }
 

@@ -54,6 +54,9 @@ class _Batch(ctypes.Structure):
         ("steps", ctypes.c_void_p),
         ("seed", ctypes.c_void_p),
         ("env_id", ctypes.c_void_p),
+        ("disc_off", ctypes.c_void_p),
+        ("disc_total", ctypes.c_int64),
+        ("disc", ctypes.c_void_p),
     ]
 
 
@@ -65,7 +68,7 @@ def _bind(path: str):
     L.or_reset.restype = ctypes.c_int
     L.or_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.c_uint64, ctypes.c_void_p]
     L.or_step.restype = None
-    L.or_step.argtypes = [ctypes.POINTER(_Batch), ctypes.c_int, ctypes.c_void_p,
+    L.or_step.argtypes = [ctypes.POINTER(_Batch), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.or_observe_all.restype = None
     L.or_observe_all.argtypes = [ctypes.POINTER(_Batch), ctypes.c_void_p]
@@ -149,6 +152,14 @@ class OracleBatch:
             self.obs_off[1:] = np.cumsum(per_obs)[:-1]
         self.agents_total = int(n.sum())
         self.obs_total = int(per_obs.sum())
+        # discovery maps of exploring envs (flag 16): H rows of ceil(W/32) words
+        flags = self.spec[:, 7]
+        per_map = np.where(flags & 16, H.astype(np.int64) * ((W.astype(np.int64) + 31) // 32), 0)
+        self.disc_off = np.zeros(ne, np.int64)
+        if ne > 1:
+            self.disc_off[1:] = np.cumsum(per_map)[:-1]
+        self.disc_total = int(per_map.sum())
+        self.disc = np.zeros(max(self.disc_total, 1), np.uint32)
         self.walls = np.zeros(int(cells.sum()), np.uint8)
         self.px = np.zeros(self.agents_total, np.uint8)
         self.py = np.zeros(self.agents_total, np.uint8)
@@ -166,7 +177,8 @@ class OracleBatch:
             self.obs_off.ctypes.data, self.agents_total, self.obs_total,
             self.walls.ctypes.data, self.px.ctypes.data, self.py.ctypes.data,
             self.found.ctypes.data, self.t.ctypes.data, self.ep.ctypes.data,
-            self.steps.ctypes.data, self.seed.ctypes.data, self.env_id.ctypes.data)
+            self.steps.ctypes.data, self.seed.ctypes.data, self.env_id.ctypes.data,
+            self.disc_off.ctypes.data, self.disc_total, self.disc.ctypes.data)
 
     def reset(self, seed: int) -> np.ndarray:
         obs0 = np.zeros(self.obs_total, np.uint32)
@@ -175,17 +187,21 @@ class OracleBatch:
             raise ValueError(f"env {-rc - 1} has fewer free cells than agents")
         return obs0
 
-    def step(self, n_steps: int = 1, actions=None):
+    def step(self, n_steps: int = 1, actions=None, maps: bool = False):
+        """(obs, rew, done) of n_steps steps, plus the discovery maps
+        [n_steps][disc_total] when maps is true."""
         obs = np.zeros((n_steps, self.obs_total), np.uint32)
         rew = np.zeros((n_steps, self.agents_total), np.float32)
         done = np.zeros((n_steps, self.n_envs), np.uint8)
+        mp = np.zeros((n_steps, self.disc_total), np.uint32) if maps else None
         aptr = None
         if actions is not None:
             actions = np.ascontiguousarray(actions, dtype=np.int8).reshape(n_steps, self.agents_total)
             aptr = actions.ctypes.data
         self._lib.or_step(ctypes.byref(self._c), int(n_steps), aptr, obs.ctypes.data,
-                      rew.ctypes.data, done.ctypes.data)
-        return obs, rew, done
+                          rew.ctypes.data, done.ctypes.data,
+                          mp.ctypes.data if maps and self.disc_total else None)
+        return (obs, rew, done, mp) if maps else (obs, rew, done)
 
     def observe(self) -> np.ndarray:
         obs = np.zeros(self.obs_total, np.uint32)
@@ -196,7 +212,8 @@ class OracleBatch:
     def get_state(self) -> dict:
         return dict(walls=self.walls.copy(), pos_x=self.px.copy(), pos_y=self.py.copy(),
                     found=self.found.copy(), t=self.t.copy(), episode=self.ep.copy(),
-                    steps=self.steps.copy(), seed=self.seed.copy(), env_id=self.env_id.copy())
+                    steps=self.steps.copy(), seed=self.seed.copy(), env_id=self.env_id.copy(),
+                    discovered=self.disc[:self.disc_total].copy())
 
     def set_state(self, st: dict) -> None:
         self.walls[:] = st["walls"]
@@ -208,6 +225,8 @@ class OracleBatch:
         self.steps[:] = st["steps"]
         self.seed[:] = st["seed"]
         self.env_id[:] = st["env_id"]
+        if "discovered" in st:  # optional: exploring envs' discovery maps
+            self.disc[:self.disc_total] = st["discovered"]
 
 
 def spawn(spec: dict, walls: np.ndarray, seed: int, env: int, episode: int):

@@ -21,6 +21,7 @@ Rules restated (see the step rules documented with the library):
 """
 from __future__ import annotations
 
+import functools
 import itertools
 
 import numpy as np
@@ -30,6 +31,7 @@ DY = np.array([0, -1, 1, 0, 0])
 OCCLUDE = 8
 
 
+@functools.lru_cache(maxsize=None)
 def crossed_cells(dx, dy, N=48):
     """Cells (ex, ey), other than (0, 0) and (dx, dy), whose open unit square
     holds a point of the open segment from (0, 0) to (dx, dy), found by

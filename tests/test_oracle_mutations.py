@@ -10,6 +10,7 @@ import pytest
 
 from oracle import oracle as o
 from tests import bruteforce_spec as bf
+from tests import test_oracle_explore as explore
 from tests import test_oracle_golden as golden
 from tests import test_oracle_rng as rng
 
@@ -32,7 +33,7 @@ MUTATIONS = {
     "respawn_old_episode": ("or_spawn(sp, walls, px, py, seed, env, b->ep[e]);",
                             "or_spawn(sp, walls, px, py, seed, env, b->ep[e] - 1);"),
     "action_keyed_by_t": ("b->steps[e], 0, i & 3), 5u);", "b->t[e], 0, i & 3), 5u);"),
-    "obs_before_reset": ("    /* 5 auto-reset */\n    if (d) {",
+    "obs_before_reset": ("    /* 5 auto-reset (the new episode's discovery map is empty) */\n    if (d) {",
                          "    or_observe(sp, walls, px, py, obs);\n    if (0) {"),
     "opponent_as_teammate": ("if (or_is_seeker(j, S) == or_is_seeker(i, S))", "if (1)"),
     "los_corner_touch_blocks": ("return a.num * b.den < b.num * a.den;",
@@ -43,6 +44,15 @@ MUTATIONS = {
                                         "lo->num = -(2 * e - 1); lo->den = -2 * d;"),
     "los_outside_not_blocking": ("int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx];",
                                  "int blocking = or_in_bounds(bx, by, W, H) && walls[by * W + bx];"),
+    "explore_counted_after_update": ("if (pass == 0) {", "if (pass == 1) {"),
+    "hiders_explore": ("for (int i = 0; i < S && i < n; ++i) {", "for (int i = 0; i < n; ++i) {"),
+    "explore_map_kept_at_auto_reset": (
+        "        b->found[e] = 0;\n        if (flags & OR_EXPLORE)\n            memset(",
+        "        b->found[e] = 0;\n        if (0)\n            memset("),
+    "explore_ignores_occlusion": (
+        "if ((flags & OR_OCCLUDE) && !or_visible(sp, walls, px[i], py[i], cx, cy))\n                            continue;",
+        "if (0)\n                            continue;"),
+    "explore_reward_scale": ("0.0078125f", "0.00390625f"),
     "detection_ignores_los": (
         "int vis = !(flags & OR_OCCLUDE) || or_visible(sp, walls, px[i], py[i], px[h], py[h]);",
         "int vis = 1;"),
@@ -96,7 +106,11 @@ def run_pins(libpath, rocrand_philox):
 
     pins = [("golden", golden_pin), ("bruteforce", brute_pin), ("philox", philox_pin),
             ("streams", lambda: rng.check_stream_layout(rocrand_philox, libpath)),
-            ("respawn", lambda: rng.check_respawn_keyed_by_episode(rocrand_philox, libpath))]
+            ("respawn", lambda: rng.check_respawn_keyed_by_episode(rocrand_philox, libpath)),
+            ("explore_golden", lambda: explore.check_hand_worked(libpath)),
+            ("explore_restated", lambda: explore.check_restated(False, libpath, n_envs=6, steps=60)),
+            ("explore_restated_occluded",
+             lambda: explore.check_restated(True, libpath, n_envs=6, steps=60))]
     for name, fn in pins:
         try:
             fn()

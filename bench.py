@@ -36,6 +36,9 @@ DESCR = {
     "small": "1024 envs, 16x16 grid, 10% iid walls, 1 seeker + 1 hider, 5x5 window, 3 channels",
     "los16k": "16384 envs, 32x32 grid, 15% iid walls, 1 seeker + 1 hider, 7x7 window with "
               "line-of-sight occlusion, 3 bit-packed channels, episode 256",
+    "explore16k": "16384 envs, 32x32 grid, 15% iid walls, 1 seeker + 1 hider, 7x7 window, "
+                  "3 bit-packed channels, episode 256, exploration rewards, per-step "
+                  "discovery-map output (32 words per env)",
     "multi10": "4096 envs, 32x32 grid, 15% iid walls, 5 seekers + 5 hiders, 9x9 window, "
                "4 channels, collisions in agent order",
     "uneven8k": "8192 envs: sides {16,32,64} (50/30/20%), 1..10 agents, 5..25% walls, "
@@ -48,21 +51,34 @@ def words(r: int) -> int:
     return (d * d + 31) // 32
 
 
-def out_bytes_per_step(specs) -> int:
+EXPLORE = 16
+
+
+def map_bytes(s) -> int:
+    """Bytes of an env's discovery map (0 unless it explores)."""
+    return 4 * s["H"] * ((s["W"] + 31) // 32) if s["flags"] & EXPLORE else 0
+
+
+def out_bytes_per_step(specs, maps: bool = False) -> int:
     """Algorithmic output bytes of one step: packed obs words, one float32
-    reward per agent, one uint8 done per env."""
-    return sum(4 * s["n"] * s["C"] * words(s["r"]) + 4 * s["n"] + 1 for s in specs)
+    reward per agent, one uint8 done per env and, with map output, the
+    discovery maps of exploring envs."""
+    return sum(4 * s["n"] * s["C"] * words(s["r"]) + 4 * s["n"] + 1 + (map_bytes(s) if maps else 0)
+               for s in specs)
 
 
 def state_bytes_per_launch(specs) -> int:
     """Bytes a launch must read and write once: per-env spec/offset/key words
-    and counters (read 56 B, write 16 B), agent positions (2 B each way), and the
-    padded wall bitboard (read)."""
+    and counters (read 56 B, plus the map offset for envs with line of sight
+    or exploration; write 16 B), agent positions (2 B each way), the padded
+    wall bitboard (read) and the discovery map of an exploring env (read and
+    write)."""
     tot = 0
     for s in specs:
         P = (s["W"] + 8 + 31) // 32
         board = 4 * ((s["H"] + 8) * P + 1)
-        tot += 56 + 16 + 4 * s["n"] + board
+        feat = 4 if s["flags"] & (8 | EXPLORE) else 0
+        tot += 56 + feat + 16 + 4 * s["n"] + board + 2 * map_bytes(s)
     return tot
 
 
@@ -157,6 +173,8 @@ def main():
                     help="choose the tiling with the autotuner (timed runs of STEPS steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-launch", action="store_true")
+    ap.add_argument("--no-maps", action="store_true",
+                    help="exploring workloads: skip the per-step discovery-map output")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (calibrates the "
                          "HBM traffic counters) and exit")
@@ -193,14 +211,16 @@ def main():
     g.reset(w["seed"])
     if args.autotune:
         lanes = g.autotune(args.autotune)
+    maps_on = g.map_words > 0 and not args.no_maps
     obs, rew, done = g.alloc_outputs(K)
+    mp = g.alloc_outputs(K, maps=True)[3] if maps_on else None
     if W > 0:
-        g.step_into(obs, rew, done, W)
-    g.prepare(obs, rew, done, K)
+        g.step_into(obs, rew, done, W, maps=mp)
+    g.prepare(obs, rew, done, K, maps=mp)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    g.step_into(obs, rew, done, K)
+    g.step_into(obs, rew, done, K, maps=mp)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
@@ -211,10 +231,10 @@ def main():
         g2 = hase.HaseBatch(specs, device="cuda:0", lanes=lanes)
         g2.reset(w["seed"])
         if W > 0:
-            g2.step_into(obs, rew, done, min(W, K), mode=hase.PER_LAUNCH)
+            g2.step_into(obs, rew, done, min(W, K), mode=hase.PER_LAUNCH, maps=mp)
         torch.cuda.synchronize()
         ev0.record(stream)
-        g2.step_into(obs, rew, done, K, mode=hase.PER_LAUNCH)
+        g2.step_into(obs, rew, done, K, mode=hase.PER_LAUNCH, maps=mp)
         ev1.record(stream)
         torch.cuda.synchronize()
         ms_pl = ev0.elapsed_time(ev1)
@@ -222,7 +242,7 @@ def main():
                           unit="agent-steps/s")
         g2.close()
 
-    alg_bytes = K * out_bytes_per_step(specs) + state_bytes_per_launch(specs)
+    alg_bytes = K * out_bytes_per_step(specs, maps_on) + state_bytes_per_launch(specs)
     achieved = alg_bytes / (ms / 1e3) / 1e9
     traffic = traffic_from_profiles(args.workload, K)
     line = {
@@ -240,7 +260,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {DESCR[args.workload]}", "n_envs": n_envs,
                    "agents": agents, "steps_per_call": K, "launch": "persistent hipGraph",
-                   "lanes_per_env": g.get_tiling()},
+                   "lanes_per_env": g.get_tiling(), "map_output": maps_on},
         "env_steps_per_s": n_envs * K / (ms / 1e3),
         "per_launch": per_launch,
         "persistent_speedup": (value / per_launch["value"]) if per_launch else None,

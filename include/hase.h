@@ -58,6 +58,15 @@ extern "C" {
  * hidden cells read 0 in every channel and a seeker sees a hider only if the
  * hider's cell is visible */
 #define HASE_OCCLUDE 8u
+/* exploration (Sec. 3.1 intrinsic reward for undiscovered tiles; Sec. 3.3
+ * centralised observation; the discovery-map layer of the observation tensor
+ * table): each env keeps a discovery map of the cells its seekers have seen
+ * this episode (empty at every episode start); after the moves of a step a
+ * seeker earns 1/128 per cell of its window (inside the map, visible under
+ * HASE_OCCLUDE) absent from the map before that step, then those cells join
+ * the map; its reward is (128 * detections + new cells) / 128. The map after
+ * each step is the optional output of hase_step_maps. */
+#define HASE_EXPLORE 16u
 
 /* step modes */
 #define HASE_STEP_PERSISTENT 0u  /* all n_steps in one launch per tile variant (graph-replayed) */
@@ -107,6 +116,11 @@ typedef struct hase_batch_desc {
  *         same role, 2 an agent of the other role, 3 outside the map.
  *   rew   agents_total float32: env e's agents start at agent_off[e]
  *   done  n_envs uint8: bit 0 terminated, bit 1 truncated
+ *   map   (hase_step_maps only) map_words_per_step uint32: the discovery map
+ *         of every HASE_EXPLORE env after the step (other envs take no
+ *         words), env e's at word map_off[e] (hase_get_map_offsets): H rows
+ *         of ceil(W/32) words, cell (x, y) at bit x & 31 of word
+ *         y * ceil(W/32) + x / 32, bits past W are 0
  * and external actions are agents_total int8 per step.
  * state_bytes is the device buffer hase_create needs; cells_total the
  * number of grid cells (walls array of the host state).
@@ -117,6 +131,7 @@ typedef struct hase_layout {
     uint64_t agents_total;
     uint64_t n_envs;
     uint64_t cells_total;
+    uint64_t map_words_per_step;
 } hase_layout;
 
 /*
@@ -129,6 +144,10 @@ typedef struct hase_layout {
  *   episode  [n_envs] episode index since the reset
  *   steps    [n_envs] step calls since the reset (the generator's step key)
  *   seed     [n_envs] generator seed
+ *   discovered [map_words_per_step] discovery maps of the HASE_EXPLORE envs
+ *            (the map layout above); may be NULL: get_state then skips the
+ *            maps and set_state clears every map; set_state rejects a map
+ *            with bits past the width (HASE_ESTATE)
  * Env ids are not part of the state: they come from the batch descriptor.
  */
 typedef struct hase_host_state {
@@ -136,6 +155,7 @@ typedef struct hase_host_state {
     uint8_t *pos_x, *pos_y;
     uint32_t *found, *t, *episode, *steps;
     uint64_t *seed;
+    uint32_t *discovered;
 } hase_host_state;
 
 typedef struct hase_batch hase_batch;
@@ -154,6 +174,11 @@ int hase_create(const hase_batch_desc *desc, void *d_state, uint64_t state_bytes
 
 /* Copy the per-env output offsets (words / agents) into host arrays [n_envs]. */
 int hase_get_offsets(const hase_batch *b, uint64_t *h_obs_off, uint64_t *h_agent_off);
+
+/* First map word of every env in one step's map output (hase_step_maps) and
+ * in the state's discovered array; envs without HASE_EXPLORE take 0 words.
+ * h_map_off: [n_envs] host array. */
+int hase_get_map_offsets(const hase_batch *b, uint64_t *h_map_off);
 
 /*
  * reset(seed) of every env (Sec. 3.3 desynchronised start, Sec. 4.2 grid):
@@ -176,23 +201,33 @@ int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0);
  *   d_done     [n_steps][n_envs] uint8
  *   mode       HASE_STEP_PERSISTENT or HASE_STEP_PER_LAUNCH (identical results)
  * Enqueued on the stream; output buffers must not overlap the state. A
- * persistent call is one kernel launch per variant group (all n_steps
- * inside): a batch with one group replays a captured graph, a batch with
- * several launches them directly on forked streams joined back into the
- * stream, so the groups run concurrently.
+ * persistent call replays a captured graph with one kernel launch per
+ * variant group (all n_steps inside); the groups sit on parallel branches
+ * and run concurrently.
  */
 int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
               float *d_rew, uint8_t *d_done, uint32_t mode);
 
 /*
+ * hase_step plus the centralised observation of HASE_EXPLORE envs:
+ *   d_map  [n_steps][map_words_per_step] uint32 (the map layout of
+ *          hase_layout), the discovery maps after each step; NULL = no map
+ *          output (then identical to hase_step)
+ * Same argument rules and launch behaviour as hase_step.
+ */
+int hase_step_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
+                   float *d_rew, uint8_t *d_done, uint32_t *d_map, uint32_t mode);
+
+/*
  * Capture (if not cached) the persistent step graph for exactly these
- * arguments without launching it, so a later hase_step with the same
- * arguments only replays it (no capture cost on the critical path); for a
- * batch with several variant groups it only creates the side streams. Same
- * argument rules as hase_step; enqueues nothing.
+ * arguments without launching it, so a later persistent hase_step (or
+ * hase_step_maps, with the same d_map) only replays it: no capture cost on
+ * the critical path. Same argument rules as hase_step; enqueues nothing.
  */
 int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
                  float *d_rew, uint8_t *d_done);
+int hase_prepare_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
+                      float *d_rew, uint8_t *d_done, uint32_t *d_map);
 
 /* Observation of the current state (e.g. after hase_set_state); enqueued. */
 int hase_observe(hase_batch *b, uint32_t *d_obs);
@@ -231,7 +266,8 @@ int hase_autotune(hase_batch *b, uint32_t n_steps, uint32_t *d_obs, float *d_rew
  * together, one launch per lanes-per-env value across all of them. Request i
  * takes io[i].n_steps <= n_steps steps; its outputs (and optional actions)
  * are indexed by output step io[i].out_step0 + k in its own buffers, laid out
- * as for hase_step. Handles must be distinct and not in use elsewhere; the
+ * as for hase_step, and d_map (may be NULL) as for hase_step_maps. Handles
+ * must be distinct and not in use elsewhere; the
  * work is enqueued on `stream` (a hipStream_t): with more than one lanes
  * value the launches run concurrently on side streams of io[0].batch,
  * forked from and joined back into `stream`. d_workspace is caller device
@@ -246,6 +282,7 @@ typedef struct hase_step_io {
     uint32_t *d_obs;
     float *d_rew;
     uint8_t *d_done;
+    uint32_t *d_map;
 } hase_step_io;
 
 int hase_multi_workspace(hase_batch *const *batches, uint32_t n, uint64_t *bytes);

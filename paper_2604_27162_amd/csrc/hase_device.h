@@ -510,67 +510,194 @@ __device__ __forceinline__ void los_visible(const uint32_t (&wall)[W], uint32_t 
     for (int w = 0; w < W; ++w) vis[w] = ~occ[w];
 }
 
-// Channels of one agent (agent_masks_raw), and with line of sight (OCC)
-// every channel restricted to the visible cells and the opponent count
-// restricted to visible opponents.
-template <int R, int W, int NMAX, bool EXACT, bool OCC>
-__device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
-                                           const int (&pp)[NMAX], int a, int pa, int n, int S,
-                                           bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
-                                           uint32_t (&team)[W], uint32_t (&opp)[W])
+// Line of sight: the channels of one agent restricted to the cells visible
+// from its own (vis, from the wall|outside window), and the count of the
+// visible opponents.
+template <int R, int W, int NMAX, bool EXACT>
+__device__ __forceinline__ int occlude(const int (&pp)[NMAX], int a, int pa, int n, int S,
+                                       uint32_t (&wall)[W], uint32_t (&outm)[W], uint32_t (&team)[W],
+                                       uint32_t (&opp)[W], uint32_t (&vis)[W])
 {
-    int cnt = agent_masks_raw<R, W, NMAX, EXACT>(slot, H, Wd, pp, a, pa, n, S, want_out, wall,
-                                                 outm, team, opp);
-    if constexpr (OCC) {
-        uint32_t vis[W];
-        los_visible<R, W>(wall, vis);
+    los_visible<R, W>(wall, vis);
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            wall[i] &= vis[i];
-            outm[i] &= vis[i];
-            team[i] &= vis[i];
-            opp[i] &= vis[i];
-        }
-        if constexpr (!EXACT) {
-            // distinct cells: one opponent per opponent bit
-            cnt = 0;
+    for (int i = 0; i < W; ++i) {
+        wall[i] &= vis[i];
+        outm[i] &= vis[i];
+        team[i] &= vis[i];
+        opp[i] &= vis[i];
+    }
+    int cnt = 0;
+    if constexpr (!EXACT) {
+        // distinct cells: one opponent per opponent bit
 #pragma unroll
-            for (int i = 0; i < W; ++i) cnt += __builtin_popcount(opp[i]);
-        } else {
-            // agents may share cells: count visible opponents one by one
-            constexpr int D = 2 * R + 1;
-            const int ax = pa & 0xff, ay = pa >> 8;
-            const bool sa = a < S;
-            cnt = 0;
+        for (int i = 0; i < W; ++i) cnt += __builtin_popcount(opp[i]);
+    } else {
+        // agents may share cells: count visible opponents one by one
+        constexpr int D = 2 * R + 1;
+        const int ax = pa & 0xff, ay = pa >> 8;
+        const bool sa = a < S;
 #pragma unroll
-            for (int j = 0; j < NMAX; ++j) {
-                const int dx = (pp[j] & 0xff) - ax + R;
-                const int dy = (pp[j] >> 8) - ay + R;
-                const bool in = j < n && j != a && (uint32_t)dx < (uint32_t)D &&
-                                (uint32_t)dy < (uint32_t)D && ((j < S) != sa);
-                const int kk = in ? dy * D + dx : 0;
-                uint32_t vw = vis[0];
+        for (int j = 0; j < NMAX; ++j) {
+            const int dx = (pp[j] & 0xff) - ax + R;
+            const int dy = (pp[j] >> 8) - ay + R;
+            const bool in = j < n && j != a && (uint32_t)dx < (uint32_t)D &&
+                            (uint32_t)dy < (uint32_t)D && ((j < S) != sa);
+            const int kk = in ? dy * D + dx : 0;
+            uint32_t vw = vis[0];
 #pragma unroll
-                for (int i = 1; i < W; ++i) vw = (kk >> 5) == i ? vis[i] : vw;
-                cnt += (in && ((vw >> (kk & 31)) & 1u)) ? 1 : 0;
-            }
+            for (int i = 1; i < W; ++i) vw = (kk >> 5) == i ? vis[i] : vw;
+            cnt += (in && ((vw >> (kk & 31)) & 1u)) ? 1 : 0;
         }
     }
     return cnt;
 }
 
-template <int R, int W, int NMAX, int TPL, bool EXACT, bool OCC>
+// Channels of one agent (agent_masks_raw). The feature loop (FEAT) adds the
+// per-env options: with line of sight (occl) every channel is restricted to
+// the visible cells and the opponent count to visible opponents; with
+// exploration (xpl) seen gets the window cells that are visible and inside
+// the map (bits past the window's D*D cells are undefined).
+template <int R, int W, int NMAX, bool EXACT, bool FEAT>
+__device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
+                                           const int (&pp)[NMAX], int a, int pa, int n, int S,
+                                           bool want_out, bool occl, bool xpl, uint32_t (&wall)[W],
+                                           uint32_t (&outm)[W], uint32_t (&team)[W],
+                                           uint32_t (&opp)[W], uint32_t (&seen)[W])
+{
+    // exploration needs the outside-the-map cells whatever the channel count
+    // (outm is stored only for 4-channel envs)
+    int cnt = agent_masks_raw<R, W, NMAX, EXACT>(slot, H, Wd, pp, a, pa, n, S,
+                                                 FEAT ? (want_out || xpl) : want_out, wall, outm,
+                                                 team, opp);
+    if constexpr (FEAT) {
+        uint32_t vis[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) vis[i] = 0xffffffffu;
+        if (occl) cnt = occlude<R, W, NMAX, EXACT>(pp, a, pa, n, S, wall, outm, team, opp, vis);
+#pragma unroll
+        for (int i = 0; i < W; ++i) seen[i] = vis[i] & ~outm[i];
+    }
+    return cnt;
+}
+
+template <int R, int W, int NMAX, int TPL, bool EXACT, bool FEAT>
 __device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
                                           const int (&pp)[NMAX], int l, int lanes,
                                           const int (&mine)[TPL], int n, int S, bool want_out,
-                                          uint32_t (&wall)[TPL][W], uint32_t (&outm)[TPL][W],
-                                          uint32_t (&team)[TPL][W], uint32_t (&opp)[TPL][W],
+                                          bool occl, bool xpl, uint32_t (&wall)[TPL][W],
+                                          uint32_t (&outm)[TPL][W], uint32_t (&team)[TPL][W],
+                                          uint32_t (&opp)[TPL][W], uint32_t (&seen)[TPL][W],
                                           int (&cnt)[TPL])
 {
 #pragma unroll
     for (int m = 0; m < TPL; ++m)
-        cnt[m] = agent_masks<R, W, NMAX, EXACT, OCC>(slot, H, Wd, pp, l + m * lanes, mine[m], n, S,
-                                                want_out, wall[m], outm[m], team[m], opp[m]);
+        cnt[m] = agent_masks<R, W, NMAX, EXACT, FEAT>(slot, H, Wd, pp, l + m * lanes, mine[m], n,
+                                                      S, want_out, occl, xpl, wall[m], outm[m],
+                                                      team[m], opp[m], seen[m]);
+}
+
+// ------------------------------------------------------------ exploration
+
+// Row rho of a window mask (D bits).
+template <int R, int W>
+__device__ __forceinline__ uint32_t window_row(const uint32_t (&m)[W], int rho)
+{
+    constexpr int D = 2 * R + 1;
+    const int off = rho * D, wi = off >> 5, b = off & 31;
+    uint32_t v = m[wi] >> b;
+    if (b + D > 32) v |= m[wi + 1] << (32 - b);
+    return v & ((1u << D) - 1u);
+}
+
+// Cells of a seeker's seen window (agent at packed padded cell pa) that the
+// env's discovery map (LDS, padded board layout) does not hold yet.
+template <int R, int W>
+__device__ __forceinline__ int explore_fresh(const uint32_t *map, int pa, const uint32_t (&seen)[W])
+{
+    constexpr int D = 2 * R + 1;
+    const int col = (pa & 0xff) - R;
+    const uint32_t *base = map + ((pa >> 8) - R) * LDS_ROW + (col >> 5);
+    const uint32_t sh = (uint32_t)(col & 31);
+    int f = 0;
+#pragma unroll
+    for (int rho = 0; rho < D; ++rho) {
+        const uint32_t *rp = base + rho * LDS_ROW;
+        const uint32_t old = __builtin_amdgcn_alignbit(rp[1], rp[0], sh);
+        f += __builtin_popcount(window_row<R, W>(seen, rho) & ~old);
+    }
+    return f;
+}
+
+// Add a seeker's seen window to the discovery map. Seekers of one env share
+// the map words (several lanes, or one lane's tasks), hence LDS atomics.
+template <int R, int W>
+__device__ __forceinline__ void explore_mark(uint32_t *map, int pa, const uint32_t (&seen)[W])
+{
+    constexpr int D = 2 * R + 1;
+    const int col = (pa & 0xff) - R;
+    uint32_t *base = map + ((pa >> 8) - R) * LDS_ROW + (col >> 5);
+    const uint32_t sh = (uint32_t)(col & 31);
+#pragma unroll
+    for (int rho = 0; rho < D; ++rho) {
+        uint32_t *rp = base + rho * LDS_ROW;
+        const uint64_t v = (uint64_t)window_row<R, W>(seen, rho) << sh;
+        __hip_atomic_fetch_or(rp, (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_or(rp + 1, (uint32_t)(v >> 32), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// LDS discovery map (padded layout) -> HBM map of H rows of ceil(W/32) words
+// (1 or 2), split over the env's lanes in chunks of 4 consecutive words (one
+// 16-byte store each; the words past the map in the last chunk are read from
+// padding rows and not stored).
+template <int LANES>
+__device__ __forceinline__ void map_store(GAS uint32_t *dst, const uint32_t *map, int H, int Wd, int l)
+{
+    const uint32_t rs = Wd > 32 ? 1u : 0u;  // log2 of the words per row
+    const uint32_t total = (uint32_t)H << rs;
+    for (uint32_t w0 = 4u * (uint32_t)l; w0 < total; w0 += 4u * LANES) {
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t w = w0 + (uint32_t)k, y = w >> rs, j = w & rs;
+            const uint32_t *row = map + (y + PAD) * LDS_ROW + j;
+            v[k] = __builtin_amdgcn_alignbit(row[1], row[0], PAD);
+        }
+        if (w0 + 4u <= total) {
+            u32x4_a4 x;
+            x.x = v[0];
+            x.y = v[1];
+            x.z = v[2];
+            x.w = v[3];
+            *(GAS u32x4_a4 *)(dst + w0) = x;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (w0 + (uint32_t)k < total) dst[w0 + k] = v[k];
+        }
+    }
+}
+
+// HBM map -> LDS discovery map (all mw words of the padded layout, rows
+// outside the map and the slack word 0), words split over the env's lanes.
+template <int LANES>
+__device__ __forceinline__ void map_load(uint32_t *map, const GAS uint32_t *src, int H, int Wd, int l)
+{
+    const int rw = (Wd + 31) >> 5;
+    const int mw = (H + 2 * PAD) * LDS_ROW + 1;
+    for (int i = l; i < mw; i += LANES) {
+        const int yy = i / LDS_ROW, j = i - yy * LDS_ROW, y = yy - PAD;
+        uint32_t v = 0u;
+        if ((uint32_t)y < (uint32_t)H) {
+            const uint32_t cur = j < rw ? src[y * rw + j] : 0u;
+            const uint32_t prev = (j >= 1 && j - 1 < rw) ? src[y * rw + j - 1] : 0u;
+            v = (cur << PAD) | (prev >> (32 - PAD));
+        }
+        map[i] = v;
+    }
 }
 
 // Blocked-move field of one agent, 5 bits: bit 0 set (action 0, stay, never
@@ -610,13 +737,15 @@ __device__ __forceinline__ uint32_t gather_blocked(int l, F field)
 }
 
 // K steps of one tile: the envs perm[tile.env0 ..] of job J, LANES lanes per
-// env, at most NMAX agents, view radius R. K == 0 writes the observation of
-// the current state only. UNROLL unrolls the step loop over each action
-// window (single-variant launches; the mixed kernel keeps one copy per
-// variant to bound its code size).
-template <int LANES, int NMAX, int R, bool UNROLL, bool OCC_OK>
+// env, at most NMAX agents, view radius R, all of kind KIND. K == 0 writes
+// the observation of the current state only. UNROLL unrolls the step loop
+// over each action window (single-variant launches; the mixed kernels keep
+// one copy per variant to bound their code size). map_words is the LDS
+// discovery map per env slot (0 when no env of the launch explores).
+template <int LANES, int NMAX, int R, bool UNROLL, int KIND>
 __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, uint32_t K,
-                                          uint32_t step_base, uint32_t slot_words, uint32_t *lds)
+                                          uint32_t step_base, uint32_t slot_words,
+                                          uint32_t map_words, uint32_t *lds)
 {
     constexpr int D = 2 * R + 1;
     constexpr int W = (D * D + 31) / 32;             // words per channel
@@ -652,6 +781,8 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     const int P = (int)((s2 >> 8) & 0xffu);
     const bool collide = (flags & 1u) != 0u;
     const bool want_out = C == 4;
+    constexpr bool FEAT_OK = KIND != KIND_PLAIN;
+    constexpr bool XPL = (KIND & KIND_EXPLORE) != 0;  // every env of the tile explores
 
     const uint32_t obs_off = gp(J.tab.obs_off)[e], agent_off = gp(J.tab.agent_off)[e];
     const uint32_t env = gp(J.tab.env_id)[e];
@@ -660,9 +791,15 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     uint32_t found = gp(J.found)[e], t = gp(J.t)[e], ep = gp(J.ep)[e], steps = gp(J.steps)[e];
 
     // this env's LDS slot: the padded bitboard, then MAX_AGENTS words where a
-    // respawn writes the new positions
-    uint32_t *slot = lds + (uint32_t)q * (slot_words + MAX_AGENTS);
+    // respawn writes the new positions, then (feature launches with an
+    // exploring env) the discovery map
+    uint32_t *slot = lds + (uint32_t)q * (slot_words + MAX_AGENTS + map_words);
     int *spawned = (int *)(slot + slot_words);
+    uint32_t *mslot = slot + slot_words + MAX_AGENTS;
+    const uint32_t map_off = XPL ? gp(J.tab.map_off)[e] : 0u;
+    if constexpr (XPL) {
+        if (K != 0u) map_load<LANES>(mslot, gp(J.disc) + map_off, H, Wd, l);
+    }
     {
         // rows of P words in HBM -> rows of LDS_ROW words (unused words 0)
         const GAS uint32_t *src = gp(J.bb) + gp(J.tab.bb_off)[e];
@@ -706,6 +843,12 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                                    : gp(J.done) + ((uint64_t)J.out_step0 + step_base) * J.env_stride + e;
     const GAS int8_t *act_p =
         J.act ? gp(J.act) + ((uint64_t)J.out_step0 + step_base) * J.agent_stride + agent_off : nullptr;
+    // per-step discovery maps of an active exploring env, when requested
+    GAS uint32_t *map_p = nullptr;
+    if constexpr (XPL) {
+        if (active && J.map != nullptr && !obs_only)
+            map_p = gp(J.map) + ((uint64_t)J.out_step0 + step_base) * J.map_stride + map_off;
+    }
 
     // Complete every load issued so far here, before the step loop: the wait
     // pass would otherwise place a vmcnt(0) wait at their first use inside the
@@ -722,13 +865,14 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     const bool has_act = J.act != nullptr;
     // per-task constants: the task's agent exists (and its env is active), its
     // bit in the hider mask, its reward sign
-    bool mine_live[TPL];
+    bool mine_live[TPL], seeker[TPL];
     uint32_t hbit[TPL];
     int rsign[TPL];
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
         const int a = l + m * LANES;
         mine_live[m] = active && a < n;
+        seeker[m] = a < S;
         hbit[m] = (a < n && a >= S) ? 1u << a : 0u;
         rsign[m] = a < S ? 1 : -1;
     }
@@ -762,14 +906,18 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // The step loop, instantiated for channels computed assuming distinct
     // agent cells (collisions on) and for the exact per-agent test; the choice
     // is made once per env, outside the loop.
-    auto run = [&](auto exact_tag, auto occ_tag) {
+    auto run = [&](auto exact_tag, auto feat_tag) {
         constexpr bool EX = decltype(exact_tag)::value;
-        // line of sight: channels and counts restricted to visible cells;
-        // detection then goes through the counts (the pairwise test knows no
-        // walls), and the loop is not unrolled (bounded code size)
-        constexpr bool OC = decltype(occ_tag)::value;
-        constexpr bool USE_PAIRS = PAIRS && !OC;
-        uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W];
+        // the feature loops (feat_tag = the env kind: exploration, line of
+        // sight, or both) are not unrolled (bounded code size); with line of
+        // sight detection goes through the counts (the pairwise test knows
+        // no walls), exploration leaves it alone
+        constexpr int FK = decltype(feat_tag)::value;
+        constexpr bool OC = FK != KIND_PLAIN;
+        constexpr bool LOS = (FK & KIND_LOS) != 0;
+        constexpr bool XP = (FK & KIND_EXPLORE) != 0;
+        constexpr bool USE_PAIRS = PAIRS && !LOS;
+        uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W], seen[TPL][W];
         int cnt[TPL];
 
         // this lane's output addresses of the current step, advanced per step
@@ -790,7 +938,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 
         if (obs_only) {
             all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                           wall, outm, team, opp, cnt);
+                                               LOS, false, wall, outm, team, opp, seen, cnt);
 #pragma unroll
             for (int m = 0; m < TPL; ++m)
                 if (mine_live[m]) store_obs(m);
@@ -871,7 +1019,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 
             // ---- 3 detection at the post-move positions, and the channels
             all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                           wall, outm, team, opp, cnt);
+                                               LOS, XP, wall, outm, team, opp, seen, cnt);
             // The role channels feed only the (predicated) stores, so the
             // compiler would compute them inside the store region; using them
             // here keeps them in the step's main block, where they fill the
@@ -883,6 +1031,30 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 #pragma unroll
                     for (int i = 0; i < W; ++i) asm volatile("" ::"v"(team[m][i]), "v"(opp[m][i]));
             }
+            // exploration: each seeker's new cells are counted against the map
+            // of the previous step (every lane's reads precede every lane's
+            // atomics: one wave, LDS in order), then all are added
+            int fresh[TPL];
+#pragma unroll
+            for (int m = 0; m < TPL; ++m) fresh[m] = 0;
+            if constexpr (XP) {
+#pragma unroll
+                for (int m = 0; m < TPL; ++m)
+                    if (seeker[m]) fresh[m] = explore_fresh<R, W>(mslot, mine[m], seen[m]);
+                wave_lds_fence();
+#pragma unroll
+                for (int m = 0; m < TPL; ++m)
+                    if (seeker[m]) explore_mark<R, W>(mslot, mine[m], seen[m]);
+                wave_lds_fence();
+            }
+            // reward of a task from its detection value v: (128 v + new cells)
+            // / 128 with exploration (exact in float32), else v
+            auto reward = [&](int m, int v) __attribute__((always_inline)) {
+                if constexpr (XP)
+                    return (float)(128 * v + fresh[m]) * 0.0078125f;
+                else
+                    return (float)v;
+            };
             float rv[TPL];
             if constexpr (USE_PAIRS) {
                 uint32_t near = 0u, seen_h = 0u;
@@ -902,13 +1074,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 }
 #pragma unroll
                 for (int m = 0; m < TPL; ++m)
-                    rv[m] = (float)(rsign[m] * __builtin_popcount(near & pinv[m]));
+                    rv[m] = reward(m, rsign[m] * __builtin_popcount(near & pinv[m]));
                 found |= seen_h;
             } else {
                 uint32_t seen_h = 0u;
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) {
-                    rv[m] = (float)(rsign[m] * cnt[m]);
+                    rv[m] = reward(m, rsign[m] * cnt[m]);
                     seen_h |= cnt[m] > 0 ? hbit[m] : 0u;
                 }
                 found |= group_or_dpp<LANES>(seen_h);
@@ -941,18 +1113,30 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 ep += 1u;
                 t = 0u;
                 found = 0u;
+                // the new episode starts with an empty discovery map
+                if constexpr (XP)
+                    for (uint32_t i = (uint32_t)l; i < map_words; i += LANES) mslot[i] = 0u;
                 spawn_agents(spawned, n, H, Wd, slot, env, k0, k1, ep);
                 wave_lds_fence();
 #pragma unroll
                 for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
                 own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-                all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                               wall, outm, team, opp, cnt);
+                all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S,
+                                                   want_out, LOS, false, wall, outm, team, opp,
+                                                   seen, cnt);
 #pragma unroll
                 for (int m = 0; m < TPL; ++m)
                     if (mine_live[m]) store_obs(m);
                 if constexpr (NBR)
                     nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field<R, W>(wall[m]); });
+            }
+            // ---- 7 the discovery map after the step (centralised observation)
+            if constexpr (XP) {
+                if (map_p != nullptr) {
+                    wave_lds_fence();
+                    map_store<LANES>(map_p, mslot, H, Wd, l);
+                    map_p += J.map_stride;
+                }
             }
             steps += 1u;
 #pragma unroll
@@ -984,29 +1168,37 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     for (uint32_t jw = 0; k < nsteps; ++k, ++jw) step((w >> (12u * jw)) & 0xfffull);
                 }
             } else {
-                uint64_t w = 0;
-                for (uint32_t k = 0; k < nsteps; ++k) {
-                    const uint32_t jw = k & (uint32_t)(LANES - 1);
-                    if (jw == 0u) w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
-                    step((w >> (12u * jw)) & 0xfffull);
+                // one window per outer iteration: a plain nested loop (a
+                // "draw when the window index wraps" test inside one loop
+                // let the compiler thread it into an irreducible loop)
+                for (uint32_t left = nsteps; left != 0u;) {
+                    const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+                    const uint32_t nw = left < (uint32_t)LANES ? left : (uint32_t)LANES;
+#pragma unroll 1
+                    for (uint32_t jw = 0; jw < nw; ++jw) step((w >> (12u * jw)) & 0xfffull);
+                    left -= nw;
                 }
             }
         } else if constexpr (WINDOWED) {
-            // lane l draws block (step + wstep, group wgroup) of the window
-            uint32_t win = 0;
-            int j = 0;
-            for (uint32_t k = 0; k < nsteps; ++k) {
-                if (j == 0) win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
-                uint64_t acts = 0;
+            // lane l draws block (step + wstep, group wgroup) of the window;
+            // one window of kb steps per outer iteration
+            for (uint32_t left = nsteps; left != 0u;) {
+                const uint32_t win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                const uint32_t nw = left < (uint32_t)kb ? left : (uint32_t)kb;
+#pragma unroll 1
+                for (uint32_t j = 0; j < nw; ++j) {
+                    uint64_t acts = 0;
 #pragma unroll
-                for (int g = 0; g < MAXCALLS; ++g) {
-                    if (g < ncalls) {
-                        const uint32_t v = (uint32_t)__shfl((int)win, q * LANES + j * ncalls + g, 64);
-                        acts |= (uint64_t)v << (12 * g);
+                    for (int g = 0; g < MAXCALLS; ++g) {
+                        if (g < ncalls) {
+                            const uint32_t v =
+                                (uint32_t)__shfl((int)win, q * LANES + (int)j * ncalls + g, 64);
+                            acts |= (uint64_t)v << (12 * g);
+                        }
                     }
+                    step(acts);
                 }
-                step(acts);
-                j = (j + 1 == kb) ? 0 : j + 1;
+                left -= nw;
             }
         } else {
             for (uint32_t k = 0; k < nsteps; ++k) {
@@ -1018,22 +1210,16 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             }
         }
     };
-    // Line of sight is compiled into the mixed kernel only (the host routes
-    // every tile with an occluding env there), with the exact per-agent
-    // channels, which are right whether or not agents may share a cell; the
-    // distinct-cell shortcut is kept for the plain loop.
-    bool occ_done = false;
-    if constexpr (OCC_OK) {
-        if ((flags & 8u) != 0u) {
-            run(std::true_type{}, std::true_type{});
-            occ_done = true;
-        }
-    }
-    if (!occ_done) {
+    // The feature loops use the exact per-agent channels, which are right
+    // whether or not agents may share a cell; the distinct-cell shortcut is
+    // kept for the plain loop.
+    if constexpr (KIND == KIND_PLAIN) {
         if (collide)
-            run(std::false_type{}, std::false_type{});
+            run(std::false_type{}, std::integral_constant<int, 0>{});
         else
-            run(std::true_type{}, std::false_type{});
+            run(std::true_type{}, std::integral_constant<int, 0>{});
+    } else {
+        run(std::true_type{}, std::integral_constant<int, KIND>{});
     }
 
     // write back the state
@@ -1051,6 +1237,10 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 gp(J.pos)[agent_off + (uint32_t)jj] = (uint16_t)(x | (y << 8));
             }
         }
+        if constexpr (XPL) {
+            wave_lds_fence();
+            map_store<LANES>(gp(J.disc) + map_off, mslot, H, Wd, l);
+        }
     }
 }
 
@@ -1064,36 +1254,39 @@ __global__ __launch_bounds__(64) void step_kernel(const Tile *__restrict__ tiles
     if (blockIdx.x >= n_tiles) return;
     const Tile tile = tiles[blockIdx.x];
     const JobDesc J = jobs ? jobs[tile.job] : job0;
-    step_tile<LANES, NMAX, R, true, false>(tile, J, K, step_base, slot_words, lds);
+    step_tile<LANES, NMAX, R, true, KIND_PLAIN>(tile, J, K, step_base, slot_words, 0u, lds);
 }
 
 // Variant code of a tile: agent-count bucket * 4 + radius - 1.
 __host__ __device__ constexpr uint32_t variant_code(int bucket, int r) { return (uint32_t)(bucket * 4 + r - 1); }
 
-template <int LANES, int B>
+template <int LANES, int B, int KIND>
 __device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobDesc &J, uint32_t K,
-                                             uint32_t step_base, uint32_t slot_words, uint32_t *lds)
+                                             uint32_t step_base, uint32_t slot_words,
+                                             uint32_t map_words, uint32_t *lds)
 {
     constexpr int NMAX = BUCKET_NMAX[B];
     if constexpr ((NMAX + LANES - 1) / LANES <= 4) {
         switch (r) {
-        case 1: step_tile<LANES, NMAX, 1, false, true>(tile, J, K, step_base, slot_words, lds); break;
-        case 2: step_tile<LANES, NMAX, 2, false, true>(tile, J, K, step_base, slot_words, lds); break;
-        case 3: step_tile<LANES, NMAX, 3, false, true>(tile, J, K, step_base, slot_words, lds); break;
-        default: step_tile<LANES, NMAX, 4, false, true>(tile, J, K, step_base, slot_words, lds); break;
+        case 1: step_tile<LANES, NMAX, 1, false, KIND>(tile, J, K, step_base, slot_words, map_words, lds); break;
+        case 2: step_tile<LANES, NMAX, 2, false, KIND>(tile, J, K, step_base, slot_words, map_words, lds); break;
+        case 3: step_tile<LANES, NMAX, 3, false, KIND>(tile, J, K, step_base, slot_words, map_words, lds); break;
+        default: step_tile<LANES, NMAX, 4, false, KIND>(tile, J, K, step_base, slot_words, map_words, lds); break;
         }
     }
 }
 
-// Mixed variants in one launch (uneven batches): each wave runs the code of
-// its own tile's (bucket, radius), chosen by a wave-uniform switch, so every
-// bucket of the batch shares the chip at once.
-template <int LANES>
+// Mixed variants in one launch (uneven batches, feature kinds): each wave
+// runs the code of its own tile's (bucket, radius), chosen by a wave-uniform
+// switch, so every bucket of the batch shares the chip at once. One kernel
+// per env kind.
+template <int LANES, int KIND>
 __global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__ tiles,
                                                         uint32_t n_tiles,
                                                         const JobDesc *__restrict__ jobs,
                                                         JobDesc job0, uint32_t K,
-                                                        uint32_t step_base, uint32_t slot_words)
+                                                        uint32_t step_base, uint32_t slot_words,
+                                                        uint32_t map_words)
 {
     extern __shared__ uint32_t lds[];
     if (blockIdx.x >= n_tiles) return;
@@ -1101,10 +1294,10 @@ __global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__
     const JobDesc J = jobs ? jobs[tile.job] : job0;
     const int bucket = (int)(tile.variant >> 2), r = (int)(tile.variant & 3u) + 1;
     switch (bucket) {
-    case 0: mixed_bucket<LANES, 0>(r, tile, J, K, step_base, slot_words, lds); break;
-    case 1: mixed_bucket<LANES, 1>(r, tile, J, K, step_base, slot_words, lds); break;
-    case 2: mixed_bucket<LANES, 2>(r, tile, J, K, step_base, slot_words, lds); break;
-    default: mixed_bucket<LANES, 3>(r, tile, J, K, step_base, slot_words, lds); break;
+    case 0: mixed_bucket<LANES, 0, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+    case 1: mixed_bucket<LANES, 1, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+    case 2: mixed_bucket<LANES, 2, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+    default: mixed_bucket<LANES, 3, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
     }
 }
 
@@ -1153,14 +1346,15 @@ inline hipError_t launch_lanes(int nmax, int r, const Tile *tiles, uint32_t n_ti
     }
 }
 
-template <int LANES>
+template <int LANES, int KIND>
 inline hipError_t launch_mixed_l(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
                                  const JobDesc &job0, uint32_t K, uint32_t step_base,
-                                 uint32_t slot_words, hipStream_t stream)
+                                 uint32_t slot_words, uint32_t map_words, hipStream_t stream)
 {
-    const size_t lds = (size_t)(64 / LANES) * (slot_words + MAX_AGENTS) * sizeof(uint32_t);
-    hipLaunchKernelGGL((step_kernel_mixed<LANES>), dim3(n_tiles), dim3(64), lds, stream, tiles,
-                       n_tiles, jobs, job0, K, step_base, slot_words);
+    const size_t lds =
+        (size_t)(64 / LANES) * (slot_words + MAX_AGENTS + map_words) * sizeof(uint32_t);
+    hipLaunchKernelGGL((step_kernel_mixed<LANES, KIND>), dim3(n_tiles), dim3(64), lds, stream,
+                       tiles, n_tiles, jobs, job0, K, step_base, slot_words, map_words);
     return hipGetLastError();
 }
 

@@ -42,7 +42,15 @@ struct EnvTables {
     const uint32_t *perm;  // tile slot -> env index (tiles group similar envs)
     const uint32_t *spec0, *spec1, *spec2;
     const uint32_t *obs_off, *agent_off, *bb_off, *grid_off, *env_id;
+    const uint32_t *map_off;  // first discovery-map word (exploring envs)
 };
+
+// Discovery map of an exploring env in HBM (state and per-step output): H
+// rows of ceil(W/32) words, cell (x, y) at bit x & 31 of word
+// y * ceil(W/32) + x / 32. In LDS the step kernel keeps it in the padded
+// board layout (rows of LDS_ROW words, bit x + PAD of padded row y + PAD), so
+// an agent's window addresses it exactly like the wall board.
+inline int map_words(int H, int W) { return H * ((W + 31) >> 5); }
 
 // One stepping job: a batch's state plus this call's output buffers. Per-step
 // output strides are in elements; outputs of env e at output step s go to
@@ -61,6 +69,9 @@ struct JobDesc {
     uint64_t obs_stride, agent_stride, env_stride;
     uint32_t k_limit;     // steps this job may take in one launch
     uint32_t out_step0;   // output step index of the job's first step in this launch
+    uint32_t *disc;       // discovery maps (state), at tab.map_off[e]
+    uint32_t *map;        // per-step map output, may be null
+    uint64_t map_stride;  // map words per output step
 };
 
 // A wave's work: envs perm[env0 .. env0 + count) of job `job` (count <= 64 /
@@ -77,35 +88,57 @@ struct InitArgs {
     uint16_t *pos;
     uint8_t *walls;
     uint32_t *bb;
+    uint32_t *disc;       // discovery maps, cleared at reset
     uint32_t *err;        // min over envs with too few free cells (reset only)
     uint64_t seed_value;
     uint32_t n_envs;
     uint32_t rebuild_only; // 1: walls/positions already loaded, only rebuild bitboards
 };
 
+// Env kinds: each kind has its own step loop and its own kernels (so the
+// register allocation of one never burdens another), and a tile holds envs
+// of one kind only.
+constexpr int KIND_PLAIN = 0;    // no line of sight, no exploration
+constexpr int KIND_EXPLORE = 1;  // bit 0: exploration
+constexpr int KIND_LOS = 2;      // bit 1: line of sight
+constexpr int N_KINDS = 4;       // plain, exploration, line of sight, both
+inline int env_kind(uint32_t flags)
+{
+    return ((flags & 8u) ? KIND_LOS : 0) | ((flags & 16u) ? KIND_EXPLORE : 0);
+}
+
 // Launch the step kernel for tile range [tile0, tile0 + n_tiles) of variant
 // (lanes, nmax, view radius r). K == 0 writes the observation of the current
-// state only.
+// state only. Every env of the range is of the plain kind.
 hipError_t launch_step(int lanes, int nmax, int r, const Tile *tiles, uint32_t n_tiles,
                        const JobDesc *jobs, const JobDesc &job0, uint32_t K,
                        uint32_t step_base, uint32_t slot_words, hipStream_t stream);
 
 // One launch over tiles of several (bucket, radius) variants that share
-// `lanes`; slot_words is the largest board among them.
-hipError_t launch_mixed(int lanes, const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
-                        const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
-                        hipStream_t stream);
+// `lanes`, all envs of kind `kind`; slot_words is the largest board among
+// them, map_words the LDS words of a discovery map per env (slot_words when
+// an env of the range explores, else 0).
+hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles,
+                        const JobDesc *jobs, const JobDesc &job0, uint32_t K, uint32_t step_base,
+                        uint32_t slot_words, uint32_t map_words, hipStream_t stream);
 
 hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 
-// Per-lanes entry points, one translation unit each (hase_step_l<L>.hip).
+// Per-lanes entry points, one translation unit each: single-variant and
+// mixed plain kernels (hase_step_l<L>.hip, hase_mixed_l<L>.hip), and the
+// feature kinds (hase_feat_l<L>.hip).
 #define HASE_DECLARE_LANES(L)                                                                     \
     hipError_t launch_step_lanes##L(int nmax, int r, const Tile *tiles, uint32_t n_tiles,        \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
                                     uint32_t step_base, uint32_t slot_words, hipStream_t stream); \
     hipError_t launch_mixed_lanes##L(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,   \
                                      const JobDesc &job0, uint32_t K, uint32_t step_base,         \
-                                     uint32_t slot_words, hipStream_t stream);
+                                     uint32_t slot_words, uint32_t map_words,                     \
+                                     hipStream_t stream);                                         \
+    hipError_t launch_feat_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,               \
+                                    const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
+                                    uint32_t step_base, uint32_t slot_words, uint32_t map_words,  \
+                                    hipStream_t stream);
 HASE_DECLARE_LANES(1)
 HASE_DECLARE_LANES(2)
 HASE_DECLARE_LANES(4)

@@ -9,7 +9,8 @@ namespace hase {
 // ------------------------------------------------------------ init kernel
 
 // One 64-lane block per env: walls from the generator (reset) or loaded
-// (rebuild), padded bitboard, free-cell check, spawn of episode 0, desync.
+// (rebuild), padded bitboard, free-cell check, spawn of episode 0, desync,
+// empty discovery map (exploring envs).
 __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
 {
     __shared__ uint8_t cellw[MAX_SIDE * MAX_SIDE];
@@ -75,6 +76,10 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
     }
     __syncthreads();
     if (A.rebuild_only) return;
+    if (flags & 16u) {
+        uint32_t *map = A.disc + A.tab.map_off[e];
+        for (int i = lane; i < H * ((W + 31) >> 5); i += 64) map[i] = 0u;
+    }
 
     int f = 0;
     for (int c = lane; c < cells; c += 64) f += cellw[c] ? 0 : 1;
@@ -127,19 +132,26 @@ hipError_t launch_step(int lanes, int nmax, int r, const Tile *tiles, uint32_t n
     }
 }
 
-hipError_t launch_mixed(int lanes, const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
-                        const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
-                        hipStream_t stream)
+hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles,
+                        const JobDesc *jobs, const JobDesc &job0, uint32_t K, uint32_t step_base,
+                        uint32_t slot_words, uint32_t map_words, hipStream_t stream)
 {
     if (n_tiles == 0) return hipSuccess;
+#define HASE_MIXED_CASE(L)                                                                          \
+    case L:                                                                                         \
+        return kind == 0 ? launch_mixed_lanes##L(tiles, n_tiles, jobs, job0, K, step_base,          \
+                                                 slot_words, map_words, stream)                     \
+                         : launch_feat_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base,     \
+                                                slot_words, map_words, stream);
     switch (lanes) {
-    case 1: return launch_mixed_lanes1(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
-    case 2: return launch_mixed_lanes2(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
-    case 4: return launch_mixed_lanes4(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
-    case 8: return launch_mixed_lanes8(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
-    case 16: return launch_mixed_lanes16(tiles, n_tiles, jobs, job0, K, step_base, slot_words, stream);
+    HASE_MIXED_CASE(1)
+    HASE_MIXED_CASE(2)
+    HASE_MIXED_CASE(4)
+    HASE_MIXED_CASE(8)
+    HASE_MIXED_CASE(16)
     default: return hipErrorInvalidValue;
     }
+#undef HASE_MIXED_CASE
 }
 
 hipError_t launch_init(const InitArgs &a, hipStream_t stream)

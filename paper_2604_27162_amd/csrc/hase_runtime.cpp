@@ -3,8 +3,8 @@
 // Owns no device memory: every device byte (state, inputs, outputs) comes
 // from the caller. The state buffer is carved into structure-of-arrays regions
 // (256-byte aligned): per-env spec words, output offsets, generator keys and
-// counters, agent positions, canonical walls, padded wall bitboards, the tile
-// table and an error word. The step runs as one launch per tile variant; a
+// counters, agent positions, canonical walls, padded wall bitboards, the
+// discovery maps of exploring envs, the tile table and an error word. The step runs as one launch per tile variant; a
 // persistent call is captured once into a hipGraph (variants as concurrent
 // branches) keyed by its arguments and replayed afterwards.
 
@@ -80,20 +80,20 @@ int check_spec(const hase_env_spec &s, uint32_t idx)
     if (s.n_channels != 3 && s.n_channels != 4)
         return fail(HASE_EINVAL, "spec %u: n_channels must be 3 or 4", idx);
     if (s.wall_pct > 99) return fail(HASE_EINVAL, "spec %u: wall_pct must be <= 99", idx);
-    if (s.flags & ~15u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
+    if (s.flags & ~31u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
     if (s.episode_len < 1) return fail(HASE_EINVAL, "spec %u: episode_len must be >= 1", idx);
     return HASE_OK;
 }
 
 struct Regions {
-    size_t perm, spec0, spec1, spec2, obs_off, agent_off, bb_off, grid_off, env_id;
-    size_t seed, found, t, ep, steps, pos, walls, bb, tiles, err, total;
+    size_t perm, spec0, spec1, spec2, obs_off, agent_off, bb_off, grid_off, env_id, map_off;
+    size_t seed, found, t, ep, steps, pos, walls, bb, disc, tiles, err, total;
 };
 
 struct Plan {
     std::vector<hase_env_spec> specs;
-    std::vector<uint32_t> obs_off, agent_off, grid_off, bb_off;
-    uint64_t obs_words = 0, agents = 0, cells = 0, bb_words = 0;
+    std::vector<uint32_t> obs_off, agent_off, grid_off, bb_off, map_off;
+    uint64_t obs_words = 0, agents = 0, cells = 0, bb_words = 0, map_words = 0;
     size_t max_tiles = 0;
     Regions reg{};
 };
@@ -119,21 +119,25 @@ int make_plan(const hase_batch_desc *d, Plan &p)
     p.agent_off.resize(N);
     p.grid_off.resize(N);
     p.bb_off.resize(N);
+    p.map_off.resize(N);
     for (uint32_t e = 0; e < N; ++e) {
         const hase_env_spec &s = p.specs[e];
         p.obs_off[e] = (uint32_t)p.obs_words;
         p.agent_off[e] = (uint32_t)p.agents;
         p.grid_off[e] = (uint32_t)p.cells;
         p.bb_off[e] = (uint32_t)p.bb_words;
+        p.map_off[e] = (uint32_t)p.map_words;
         p.obs_words += (uint64_t)s.n_agents * s.n_channels * words_per_channel(s.view_radius);
         p.agents += s.n_agents;
         p.cells += (uint64_t)s.height * s.width;
         p.bb_words += (uint64_t)board_words(s.height, s.width);
+        if (s.flags & HASE_EXPLORE) p.map_words += (uint64_t)map_words(s.height, s.width);
     }
-    if (p.obs_words >= (1ull << 32) || p.cells >= (1ull << 32) || p.bb_words >= (1ull << 32))
+    if (p.obs_words >= (1ull << 32) || p.cells >= (1ull << 32) || p.bb_words >= (1ull << 32) ||
+        p.map_words >= (1ull << 32))
         return fail(HASE_EINVAL, "batch too large: per-step offsets exceed 32 bits");
     if ((uint64_t)N + 64 >= (1ull << 32)) return fail(HASE_EINVAL, "too many envs");
-    p.max_tiles = (size_t)N + MAX_VARIANTS;
+    p.max_tiles = (size_t)N + (size_t)MAX_VARIANTS * N_KINDS;
     Regions &r = p.reg;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -150,6 +154,7 @@ int make_plan(const hase_batch_desc *d, Plan &p)
     r.bb_off = take(4ull * N);
     r.grid_off = take(4ull * N);
     r.env_id = take(4ull * N);
+    r.map_off = take(4ull * N);
     r.seed = take(8ull * N);
     r.found = take(4ull * N);
     r.t = take(4ull * N);
@@ -158,6 +163,7 @@ int make_plan(const hase_batch_desc *d, Plan &p)
     r.pos = take(2ull * p.agents);
     r.walls = take(p.cells);
     r.bb = take(4ull * p.bb_words);
+    r.disc = take(4ull * p.map_words);
     r.tiles = take(sizeof(Tile) * p.max_tiles);
     r.err = take(16);
     r.total = off;
@@ -165,18 +171,22 @@ int make_plan(const hase_batch_desc *d, Plan &p)
 }
 
 // One kernel launch of a step call: a single (bucket, radius) variant, or
-// (mixed) every variant sharing `lanes`, over contiguous tiles.
+// (mixed) every variant sharing `lanes`, over contiguous tiles of envs of one
+// kind (plain, exploration, line of sight).
 struct Variant {
-    int lanes = 0, nmax = 0, r = 0;
-    // mixed: the per-tile variant switch; also required when any env of the
-    // group sets line of sight (occ), which only that kernel implements
-    bool mixed = false, occ = false;
-    uint32_t tile0 = 0, n_tiles = 0, slot_words = 0;
+    int lanes = 0, nmax = 0, r = 0, kind = KIND_PLAIN;
+    // mixed: the per-tile variant switch (the feature kinds have only that
+    // kernel); xpl: an env explores (LDS discovery maps of map_words)
+    bool mixed = false, xpl = false;
+    uint32_t tile0 = 0, n_tiles = 0, slot_words = 0, map_words = 0;
 };
+
+// lanes x kinds launches at most, each on its own stream when forked
+constexpr int MAX_LAUNCHES = 5 * N_KINDS;
 
 struct GraphEntry {
     uint32_t n_steps;
-    const void *act, *obs, *rew, *done;
+    const void *act, *obs, *rew, *done, *map;
     hipGraphExec_t exec;
 };
 
@@ -191,8 +201,8 @@ struct hase_batch {
     uint32_t lanes[N_BUCKETS];
     std::vector<Variant> variants;
     std::vector<Tile> host_tiles;  // host copy of the device tile table
-    hipStream_t side[MAX_VARIANTS] = {};
-    hipEvent_t fork_ev = nullptr, join_ev[MAX_VARIANTS] = {};
+    hipStream_t side[MAX_LAUNCHES] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[MAX_LAUNCHES] = {};
     std::list<GraphEntry> graphs;  // most recently used first
 
     template <class T>
@@ -211,6 +221,7 @@ struct hase_batch {
         t.bb_off = at<uint32_t>(r.bb_off);
         t.grid_off = at<uint32_t>(r.grid_off);
         t.env_id = at<uint32_t>(r.env_id);
+        t.map_off = at<uint32_t>(r.map_off);
         return t;
     }
 };
@@ -223,10 +234,10 @@ void drop_graphs(hase_batch *b)
     b->graphs.clear();
 }
 
-// Group envs by (agent-count bucket, view radius) -- one kernel variant each --,
-// order each group by (n, area) so a wave holds similar envs, and cut it into
-// tiles of 64 / lanes envs. Variants that share a lanes-per-env value run as
-// one mixed launch, so all buckets of an uneven batch share the chip.
+// Group envs by (kind, agent-count bucket, view radius) -- one kernel variant
+// each --, order each group by (n, area) so a wave holds similar envs, and cut
+// it into tiles of 64 / lanes envs. Variants that share a (lanes, kind) run
+// as one mixed launch, so all buckets of an uneven batch share the chip.
 int build_tiles(hase_batch *b)
 {
     const Plan &p = b->plan;
@@ -237,55 +248,60 @@ int build_tiles(hase_batch *b)
     std::vector<Variant> vars;
     const uint32_t lane_order[] = {1, 2, 4, 8, 16};
     for (uint32_t L : lane_order) {
-        Variant grp;
-        grp.lanes = (int)L;
-        grp.tile0 = (uint32_t)tiles.size();
-        int n_var = 0;
-        for (int bk = 0; bk < N_BUCKETS; ++bk) {
-            if (b->lanes[bk] != L) continue;
-            for (int r = 1; r <= PAD; ++r) {
-                std::vector<uint32_t> ids;
-                for (uint32_t e = 0; e < N; ++e)
-                    if (bucket_of(p.specs[e].n_agents) == bk && p.specs[e].view_radius == r)
-                        ids.push_back(e);
-                if (ids.empty()) continue;
-                // occluding envs together (a wave runs one loop body per flag
-                // present), then by agent count and area
-                std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
-                    const hase_env_spec &x = p.specs[a], &y = p.specs[c];
-                    const bool ox = (x.flags & HASE_OCCLUDE) != 0, oy = (y.flags & HASE_OCCLUDE) != 0;
-                    if (ox != oy) return ox;
-                    if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
-                    return x.height * x.width > y.height * y.width;
-                });
-                const uint32_t E = 64u / L;
-                const uint32_t base = (uint32_t)perm.size();
-                for (uint32_t e : ids) {
-                    perm.push_back(e);
-                    if (p.specs[e].flags & HASE_OCCLUDE) grp.occ = true;
-                    grp.slot_words = std::max(grp.slot_words, (uint32_t)lds_board_words(p.specs[e].height));
+        for (int kind = 0; kind < N_KINDS; ++kind) {
+            Variant grp;
+            grp.lanes = (int)L;
+            grp.kind = kind;
+            grp.tile0 = (uint32_t)tiles.size();
+            int n_var = 0;
+            for (int bk = 0; bk < N_BUCKETS; ++bk) {
+                if (b->lanes[bk] != L) continue;
+                for (int r = 1; r <= PAD; ++r) {
+                    std::vector<uint32_t> ids;
+                    for (uint32_t e = 0; e < N; ++e) {
+                        const hase_env_spec &s = p.specs[e];
+                        if (bucket_of(s.n_agents) == bk && s.view_radius == r &&
+                            env_kind(s.flags) == kind)
+                            ids.push_back(e);
+                    }
+                    if (ids.empty()) continue;
+                    std::stable_sort(ids.begin(), ids.end(), [&](uint32_t a, uint32_t c) {
+                        const hase_env_spec &x = p.specs[a], &y = p.specs[c];
+                        if (x.n_agents != y.n_agents) return x.n_agents > y.n_agents;
+                        return x.height * x.width > y.height * y.width;
+                    });
+                    const uint32_t E = 64u / L;
+                    const uint32_t base = (uint32_t)perm.size();
+                    for (uint32_t e : ids) {
+                        perm.push_back(e);
+                        if (p.specs[e].flags & HASE_EXPLORE) grp.xpl = true;
+                        grp.slot_words =
+                            std::max(grp.slot_words, (uint32_t)lds_board_words(p.specs[e].height));
+                    }
+                    for (uint32_t i = 0; i < ids.size(); i += E) {
+                        Tile t;
+                        t.job = 0;
+                        t.env0 = base + i;
+                        t.count = std::min<uint32_t>(E, (uint32_t)ids.size() - i);
+                        t.variant = (uint32_t)(bk * 4 + r - 1);
+                        tiles.push_back(t);
+                    }
+                    grp.nmax = BUCKET_NMAX[bk];
+                    grp.r = r;
+                    ++n_var;
                 }
-                for (uint32_t i = 0; i < ids.size(); i += E) {
-                    Tile t;
-                    t.job = 0;
-                    t.env0 = base + i;
-                    t.count = std::min<uint32_t>(E, (uint32_t)ids.size() - i);
-                    t.variant = (uint32_t)(bk * 4 + r - 1);
-                    tiles.push_back(t);
-                }
-                grp.nmax = BUCKET_NMAX[bk];
-                grp.r = r;
-                ++n_var;
             }
+            if (n_var == 0) continue;
+            grp.mixed = n_var > 1 || kind != KIND_PLAIN;
+            grp.map_words = grp.xpl ? grp.slot_words : 0u;
+            grp.n_tiles = (uint32_t)tiles.size() - grp.tile0;
+            const size_t lds_bytes =
+                (size_t)(64u / L) * (grp.slot_words + MAX_AGENTS + grp.map_words) * 4;
+            if (lds_bytes > 65536)
+                return fail(HASE_EINVAL, "tiling: %u lanes/env needs %zu bytes of LDS per wave", L,
+                            lds_bytes);
+            vars.push_back(grp);
         }
-        if (n_var == 0) continue;
-        grp.mixed = n_var > 1 || grp.occ;
-        grp.n_tiles = (uint32_t)tiles.size() - grp.tile0;
-        const size_t lds_bytes = (size_t)(64u / L) * (grp.slot_words + MAX_AGENTS) * 4;
-        if (lds_bytes > 65536)
-            return fail(HASE_EINVAL, "tiling: %u lanes/env needs %zu bytes of LDS per wave", L,
-                        lds_bytes);
-        vars.push_back(grp);
     }
     if (tiles.size() > p.max_tiles) return fail(HASE_EINVAL, "tile table overflow");
     HIP_TRY(hipMemcpyAsync(b->d + p.reg.perm, perm.data(), 4 * perm.size(), hipMemcpyHostToDevice,
@@ -299,7 +315,8 @@ int build_tiles(hase_batch *b)
     return HASE_OK;
 }
 
-JobDesc make_job(const hase_batch *b, const int8_t *act, uint32_t *obs, float *rew, uint8_t *done)
+JobDesc make_job(const hase_batch *b, const int8_t *act, uint32_t *obs, float *rew, uint8_t *done,
+                 uint32_t *map = nullptr)
 {
     const Regions &r = b->plan.reg;
     JobDesc j;
@@ -320,6 +337,9 @@ JobDesc make_job(const hase_batch *b, const int8_t *act, uint32_t *obs, float *r
     j.env_stride = b->n_envs;
     j.k_limit = 0xffffffffu;
     j.out_step0 = 0;
+    j.disc = b->at<uint32_t>(r.disc);
+    j.map = map;
+    j.map_stride = b->plan.map_words;
     return j;
 }
 
@@ -340,8 +360,8 @@ int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, h
             s = b->side[i];
         }
         if (v.mixed)
-            HIP_TRY(launch_mixed(v.lanes, tiles + v.tile0, v.n_tiles, nullptr, job, K, step_base,
-                                 v.slot_words, s));
+            HIP_TRY(launch_mixed(v.lanes, v.kind, tiles + v.tile0, v.n_tiles, nullptr, job, K,
+                                 step_base, v.slot_words, v.map_words, s));
         else
             HIP_TRY(launch_step(v.lanes, v.nmax, v.r, tiles + v.tile0, v.n_tiles, nullptr, job, K,
                                 step_base, v.slot_words, s));
@@ -357,7 +377,7 @@ int ensure_streams(hase_batch *b)
 {
     if (b->fork_ev) return HASE_OK;
     HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
-    for (int i = 0; i < MAX_VARIANTS; ++i) {
+    for (int i = 0; i < MAX_LAUNCHES; ++i) {
         HIP_TRY(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming));
     }
@@ -371,7 +391,7 @@ int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_
     if (rc) return rc;
     for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
         if (it->n_steps == n_steps && it->act == job.act && it->obs == job.obs &&
-            it->rew == job.rew && it->done == job.done) {
+            it->rew == job.rew && it->done == job.done && it->map == job.map) {
             b->graphs.splice(b->graphs.begin(), b->graphs, it);
             *out = b->graphs.front().exec;
             return HASE_OK;
@@ -392,7 +412,7 @@ int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    GraphEntry g{n_steps, job.act, job.obs, job.rew, job.done, exec};
+    GraphEntry g{n_steps, job.act, job.obs, job.rew, job.done, job.map, exec};
     b->graphs.push_front(g);
     while (b->graphs.size() > 8) {
         (void)hipGraphExecDestroy(b->graphs.back().exec);
@@ -436,6 +456,7 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
     a.pos = b->at<uint16_t>(r.pos);
     a.walls = b->at<uint8_t>(r.walls);
     a.bb = b->at<uint32_t>(r.bb);
+    a.disc = b->at<uint32_t>(r.disc);
     a.err = b->at<uint32_t>(r.err);
     a.seed_value = seed;
     a.n_envs = b->n_envs;
@@ -446,7 +467,7 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
 // Mutable per-env state (walls and bitboards never change while stepping).
 struct Snapshot {
     std::vector<uint16_t> pos;
-    std::vector<uint32_t> found, t, ep, steps;
+    std::vector<uint32_t> found, t, ep, steps, disc;
 };
 
 int snapshot_take(hase_batch *b, Snapshot &s)
@@ -458,6 +479,7 @@ int snapshot_take(hase_batch *b, Snapshot &s)
     s.t.resize(N);
     s.ep.resize(N);
     s.steps.resize(N);
+    s.disc.resize(p.map_words);
     auto down = [&](void *dst, size_t off, size_t bytes) {
         return hipMemcpyAsync(dst, b->d + off, bytes, hipMemcpyDeviceToHost, b->stream);
     };
@@ -466,6 +488,7 @@ int snapshot_take(hase_batch *b, Snapshot &s)
     HIP_TRY(down(s.t.data(), p.reg.t, 4ull * N));
     HIP_TRY(down(s.ep.data(), p.reg.ep, 4ull * N));
     HIP_TRY(down(s.steps.data(), p.reg.steps, 4ull * N));
+    if (p.map_words) HIP_TRY(down(s.disc.data(), p.reg.disc, 4ull * p.map_words));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return HASE_OK;
 }
@@ -482,6 +505,7 @@ int snapshot_restore(hase_batch *b, const Snapshot &s)
     HIP_TRY(up(p.reg.t, s.t.data(), 4ull * N));
     HIP_TRY(up(p.reg.ep, s.ep.data(), 4ull * N));
     HIP_TRY(up(p.reg.steps, s.steps.data(), 4ull * N));
+    if (p.map_words) HIP_TRY(up(p.reg.disc, s.disc.data(), 4ull * p.map_words));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return HASE_OK;
 }
@@ -534,6 +558,7 @@ int hase_query_layout(const hase_batch_desc *desc, hase_layout *out)
     out->agents_total = p.agents;
     out->n_envs = desc->n_envs;
     out->cells_total = p.cells;
+    out->map_words_per_step = p.map_words;
     return HASE_OK;
 }
 
@@ -587,6 +612,7 @@ int hase_create(const hase_batch_desc *desc, void *d_state, uint64_t state_bytes
         (e = up(p.reg.bb_off, p.bb_off.data(), 4ull * N)) != hipSuccess ||
         (e = up(p.reg.grid_off, p.grid_off.data(), 4ull * N)) != hipSuccess ||
         (e = up(p.reg.env_id, id.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.map_off, p.map_off.data(), 4ull * N)) != hipSuccess ||
         (e = hipStreamSynchronize(b->stream)) != hipSuccess) {
         delete b;
         return hip_fail(e, "hase_create upload");
@@ -607,6 +633,13 @@ int hase_get_offsets(const hase_batch *b, uint64_t *h_obs_off, uint64_t *h_agent
         if (h_obs_off) h_obs_off[e] = b->plan.obs_off[e];
         if (h_agent_off) h_agent_off[e] = b->plan.agent_off[e];
     }
+    return HASE_OK;
+}
+
+int hase_get_map_offsets(const hase_batch *b, uint64_t *h_map_off)
+{
+    if (!b || !h_map_off) return fail(HASE_EINVAL, "null argument");
+    for (uint32_t e = 0; e < b->n_envs; ++e) h_map_off[e] = b->plan.map_off[e];
     return HASE_OK;
 }
 
@@ -635,11 +668,17 @@ int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0)
 int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs, float *d_rew,
               uint8_t *d_done, uint32_t mode)
 {
+    return hase_step_maps(b, n_steps, d_actions, d_obs, d_rew, d_done, nullptr, mode);
+}
+
+int hase_step_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
+                   float *d_rew, uint8_t *d_done, uint32_t *d_map, uint32_t mode)
+{
     const int rc0 = check_step_args(b, n_steps, d_obs, d_rew, d_done);
     if (rc0) return rc0;
     if (mode != HASE_STEP_PERSISTENT && mode != HASE_STEP_PER_LAUNCH)
         return fail(HASE_EINVAL, "unknown step mode %u", mode);
-    const JobDesc job = make_job(b, d_actions, d_obs, d_rew, d_done);
+    const JobDesc job = make_job(b, d_actions, d_obs, d_rew, d_done, d_map);
     if (mode == HASE_STEP_PERSISTENT) return persistent_step(b, job, n_steps);
     if (b->variants.size() > 1) {
         const int rc = ensure_streams(b);
@@ -655,10 +694,16 @@ int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t
 int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
                  float *d_rew, uint8_t *d_done)
 {
+    return hase_prepare_maps(b, n_steps, d_actions, d_obs, d_rew, d_done, nullptr);
+}
+
+int hase_prepare_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
+                      float *d_rew, uint8_t *d_done, uint32_t *d_map)
+{
     const int rc = check_step_args(b, n_steps, d_obs, d_rew, d_done);
     if (rc) return rc;
     hipGraphExec_t exec = nullptr;
-    return graph_for(b, make_job(b, d_actions, d_obs, d_rew, d_done), n_steps, &exec);
+    return graph_for(b, make_job(b, d_actions, d_obs, d_rew, d_done, d_map), n_steps, &exec);
 }
 
 int hase_observe(hase_batch *b, uint32_t *d_obs)
@@ -688,6 +733,8 @@ int hase_get_state(hase_batch *b, const hase_host_state *out)
     HIP_TRY(down(out->episode, p.reg.ep, 4ull * N));
     HIP_TRY(down(out->steps, p.reg.steps, 4ull * N));
     HIP_TRY(down(out->seed, p.reg.seed, 8ull * N));
+    if (out->discovered && p.map_words)
+        HIP_TRY(down(out->discovered, p.reg.disc, 4ull * p.map_words));
     HIP_TRY(hipStreamSynchronize(b->stream));
     for (uint64_t i = 0; i < p.agents; ++i) {
         out->pos_x[i] = (uint8_t)(pos[i] & 0xff);
@@ -714,6 +761,15 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
                             s.height);
             pos[i] = (uint16_t)(in->pos_x[i] | (in->pos_y[i] << 8));
         }
+        if (in->discovered && (s.flags & HASE_EXPLORE)) {
+            // map bits past the width are not cells
+            const uint32_t rw = (s.width + 31) / 32, tail = s.width & 31u;
+            const uint32_t bad = tail ? ~((1u << tail) - 1u) : 0u;
+            for (uint32_t y = 0; y < s.height; ++y)
+                if (in->discovered[p.map_off[e] + y * rw + rw - 1] & bad)
+                    return fail(HASE_ESTATE, "env %u: discovery map row %u has bits past the width",
+                                e, y);
+        }
     }
     auto up = [&](size_t off, const void *src, size_t bytes) {
         return hipMemcpyAsync(b->d + off, src, bytes, hipMemcpyHostToDevice, b->stream);
@@ -725,6 +781,12 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
     HIP_TRY(up(p.reg.ep, in->episode, 4ull * N));
     HIP_TRY(up(p.reg.steps, in->steps, 4ull * N));
     HIP_TRY(up(p.reg.seed, in->seed, 8ull * N));
+    if (p.map_words) {
+        if (in->discovered)
+            HIP_TRY(up(p.reg.disc, in->discovered, 4ull * p.map_words));
+        else
+            HIP_TRY(hipMemsetAsync(b->d + p.reg.disc, 0, 4ull * p.map_words, b->stream));
+    }
     HIP_TRY(launch_init(make_init(b, 0, 1), b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->ready = true;
@@ -832,7 +894,7 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
         for (uint32_t j = 0; j < i; ++j)
             if (bs[j] == b) return fail(HASE_EINVAL, "request %u repeats a batch handle", i);
         bs[i] = b;
-        jobs[i] = make_job(b, io[i].d_actions, io[i].d_obs, io[i].d_rew, io[i].d_done);
+        jobs[i] = make_job(b, io[i].d_actions, io[i].d_obs, io[i].d_rew, io[i].d_done, io[i].d_map);
         jobs[i].k_limit = io[i].n_steps;
         jobs[i].out_step0 = io[i].out_step0;
     }
@@ -842,37 +904,46 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
     if (workspace_bytes < need)
         return fail(HASE_ENOMEM, "workspace has %llu bytes, needs %llu",
                     (unsigned long long)workspace_bytes, (unsigned long long)need);
-    // one launch group per lanes value across all requests; a group whose
-    // tiles carry more than one variant code runs the mixed kernel
+    // one launch group per (lanes, kind) across all requests; a plain group
+    // whose tiles carry more than one variant code runs the mixed kernel
     struct Group {
-        uint32_t lanes = 0, tile0 = 0, n_tiles = 0, slot = 0, code0 = 0;
-        bool mixed = false;
+        uint32_t lanes = 0, tile0 = 0, n_tiles = 0, slot = 0, map = 0, code0 = 0;
+        int kind = KIND_PLAIN;
+        bool mixed = false, xpl = false;
     };
     std::vector<Tile> tiles;
     std::vector<Group> groups;
     const uint32_t lane_order[] = {1, 2, 4, 8, 16};
     for (uint32_t L : lane_order) {
-        Group g;
-        g.lanes = L;
-        g.tile0 = (uint32_t)tiles.size();
-        for (uint32_t i = 0; i < n; ++i) {
-            for (const Variant &v : bs[i]->variants) {
-                if ((uint32_t)v.lanes != L) continue;
-                for (uint32_t t = v.tile0; t < v.tile0 + v.n_tiles; ++t) {
-                    Tile tl = bs[i]->host_tiles[t];
-                    tl.job = i;
-                    if (tiles.size() == g.tile0)
-                        g.code0 = tl.variant;
-                    else if (tl.variant != g.code0)
-                        g.mixed = true;
-                    tiles.push_back(tl);
+        for (int kind = 0; kind < N_KINDS; ++kind) {
+            Group g;
+            g.lanes = L;
+            g.kind = kind;
+            g.mixed = kind != KIND_PLAIN;  // the feature kinds have only the mixed kernel
+            g.tile0 = (uint32_t)tiles.size();
+            for (uint32_t i = 0; i < n; ++i) {
+                for (const Variant &v : bs[i]->variants) {
+                    if ((uint32_t)v.lanes != L || v.kind != kind) continue;
+                    for (uint32_t t = v.tile0; t < v.tile0 + v.n_tiles; ++t) {
+                        Tile tl = bs[i]->host_tiles[t];
+                        tl.job = i;
+                        if (tiles.size() == g.tile0)
+                            g.code0 = tl.variant;
+                        else if (tl.variant != g.code0)
+                            g.mixed = true;
+                        tiles.push_back(tl);
+                    }
+                    g.slot = std::max(g.slot, v.slot_words);
+                    if (v.xpl) g.xpl = true;
                 }
-                g.slot = std::max(g.slot, v.slot_words);
-                if (v.occ) g.mixed = true;  // line of sight: mixed kernel only
             }
+            g.map = g.xpl ? g.slot : 0u;
+            if ((size_t)(64u / L) * (g.slot + MAX_AGENTS + g.map) * 4 > 65536)
+                return fail(HASE_EINVAL,
+                            "requests with %u lanes/env need more than 64 KiB of LDS per wave", L);
+            g.n_tiles = (uint32_t)tiles.size() - g.tile0;
+            if (g.n_tiles) groups.push_back(g);
         }
-        g.n_tiles = (uint32_t)tiles.size() - g.tile0;
-        if (g.n_tiles) groups.push_back(g);
     }
     char *ws = static_cast<char *>(d_workspace);
     const size_t jobs_bytes = align256(sizeof(JobDesc) * n);
@@ -899,8 +970,8 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
             s = fb->side[gi];
         }
         if (g.mixed)
-            HIP_TRY(launch_mixed((int)g.lanes, dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps,
-                                 0, g.slot, s));
+            HIP_TRY(launch_mixed((int)g.lanes, g.kind, dtiles + g.tile0, g.n_tiles, djobs, jobs[0],
+                                 n_steps, 0, g.slot, g.map, s));
         else
             HIP_TRY(launch_step((int)g.lanes, BUCKET_NMAX[g.code0 >> 2], (int)(g.code0 & 3u) + 1,
                                 dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps, 0, g.slot, s));
@@ -916,7 +987,7 @@ int hase_destroy(hase_batch *b)
 {
     if (!b) return HASE_OK;
     drop_graphs(b);
-    for (int i = 0; i < MAX_VARIANTS; ++i) {
+    for (int i = 0; i < MAX_LAUNCHES; ++i) {
         if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
         if (b->join_ev[i]) (void)hipEventDestroy(b->join_ev[i]);
     }

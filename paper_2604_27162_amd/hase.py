@@ -6,7 +6,8 @@ HIP kernels. There is no CPU fallback: if the library is missing or cannot
 be loaded, load() raises.
 
 Layouts (per step): obs int32 words (bit-packed windows, see hase.h), rewards
-float32 per agent, dones uint8 per env (bit 0 terminated, bit 1 truncated).
+float32 per agent, dones uint8 per env (bit 0 terminated, bit 1 truncated),
+and optionally the discovery maps of exploring envs (int32 words).
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhase.so")
 
 OK, EINVAL, ENOMEM, EGRID, EHIP, ESTATE, ENOTREADY = 0, -1, -2, -3, -4, -5, -6
-COLLIDE, CAPTURE_ENDS, DESYNC, OCCLUDE = 1, 2, 4, 8
+COLLIDE, CAPTURE_ENDS, DESYNC, OCCLUDE, EXPLORE = 1, 2, 4, 8, 16
 PERSISTENT, PER_LAUNCH = 0, 1
 N_BUCKETS = 4
 
@@ -46,24 +47,26 @@ class BatchDesc(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [("state_bytes", ctypes.c_uint64), ("obs_words_per_step", ctypes.c_uint64),
                 ("agents_total", ctypes.c_uint64), ("n_envs", ctypes.c_uint64),
-                ("cells_total", ctypes.c_uint64)]
+                ("cells_total", ctypes.c_uint64), ("map_words_per_step", ctypes.c_uint64)]
 
 
 class HostState(ctypes.Structure):
     _fields_ = [("walls", ctypes.c_void_p), ("pos_x", ctypes.c_void_p),
                 ("pos_y", ctypes.c_void_p), ("found", ctypes.c_void_p), ("t", ctypes.c_void_p),
                 ("episode", ctypes.c_void_p), ("steps", ctypes.c_void_p),
-                ("seed", ctypes.c_void_p)]
+                ("seed", ctypes.c_void_p), ("discovered", ctypes.c_void_p)]
 
 
 class StepIO(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_void_p), ("n_steps", ctypes.c_uint32),
                 ("out_step0", ctypes.c_uint32), ("d_actions", ctypes.c_void_p),
-                ("d_obs", ctypes.c_void_p), ("d_rew", ctypes.c_void_p), ("d_done", ctypes.c_void_p)]
+                ("d_obs", ctypes.c_void_p), ("d_rew", ctypes.c_void_p), ("d_done", ctypes.c_void_p),
+                ("d_map", ctypes.c_void_p)]
 
 
-EXPORTS = ("hase_query_layout", "hase_create", "hase_get_offsets", "hase_reset", "hase_step",
-           "hase_prepare", "hase_observe", "hase_get_state", "hase_set_state", "hase_set_tiling",
+EXPORTS = ("hase_query_layout", "hase_create", "hase_get_offsets", "hase_get_map_offsets",
+           "hase_reset", "hase_step", "hase_step_maps", "hase_prepare", "hase_prepare_maps",
+           "hase_observe", "hase_get_state", "hase_set_state", "hase_set_tiling",
            "hase_get_tiling", "hase_autotune", "hase_multi_workspace", "hase_step_multi",
            "hase_destroy", "hase_strerror", "hase_last_error")
 
@@ -83,9 +86,12 @@ def load(path: str = LIB_PATH):
         "hase_query_layout": [ctypes.POINTER(BatchDesc), ctypes.POINTER(Layout)],
         "hase_create": [ctypes.POINTER(BatchDesc), vp, u64, vp, ctypes.POINTER(vp)],
         "hase_get_offsets": [vp, vp, vp],
+        "hase_get_map_offsets": [vp, vp],
         "hase_reset": [vp, u64, vp],
         "hase_step": [vp, u32, vp, vp, vp, vp, u32],
+        "hase_step_maps": [vp, u32, vp, vp, vp, vp, vp, u32],
         "hase_prepare": [vp, u32, vp, vp, vp, vp],
+        "hase_prepare_maps": [vp, u32, vp, vp, vp, vp, vp],
         "hase_observe": [vp, vp],
         "hase_get_state": [vp, ctypes.POINTER(HostState)],
         "hase_set_state": [vp, ctypes.POINTER(HostState)],
@@ -154,6 +160,7 @@ class HaseBatch:
         self.obs_words = int(lay.obs_words_per_step)
         self.agents = int(lay.agents_total)
         self.cells = int(lay.cells_total)
+        self.map_words = int(lay.map_words_per_step)
         self.state = torch.empty(int(lay.state_bytes), dtype=torch.uint8, device=self.device)
         if self.state.data_ptr() % 256:
             raise RuntimeError("state buffer not 256-byte aligned")
@@ -167,11 +174,15 @@ class HaseBatch:
             self.set_tiling(lanes)
 
     # -- outputs ---------------------------------------------------------
-    def alloc_outputs(self, n_steps: int):
+    def alloc_outputs(self, n_steps: int, maps: bool = False):
+        """(obs, rew, done) tensors for n_steps, plus the map tensor when maps."""
         t = self.torch
         obs = t.empty((n_steps, self.obs_words), dtype=t.int32, device=self.device)
         rew = t.empty((n_steps, self.agents), dtype=t.float32, device=self.device)
         done = t.empty((n_steps, self.n_envs), dtype=t.uint8, device=self.device)
+        if maps:
+            mp = t.empty((n_steps, max(1, self.map_words)), dtype=t.int32, device=self.device)
+            return obs, rew, done, mp
         return obs, rew, done
 
     def reset(self, seed: int):
@@ -179,12 +190,23 @@ class HaseBatch:
         _check(load().hase_reset(self._h, ctypes.c_uint64(seed), obs0.data_ptr()))
         return obs0
 
-    def step_into(self, obs, rew, done, n_steps: int, actions=None, mode: int = PERSISTENT):
-        """Enqueue n_steps into preallocated outputs (no synchronisation)."""
+    def _map_ptr(self, maps, n_steps: int):
+        if maps is None:
+            return None
+        if (maps.device != self.device or not maps.is_contiguous()
+                or maps.element_size() != 4 or maps.numel() < n_steps * self.map_words):
+            raise ValueError("map tensor has the wrong device, layout or size")
+        return maps.data_ptr()
+
+    def step_into(self, obs, rew, done, n_steps: int, actions=None, mode: int = PERSISTENT,
+                  maps=None):
+        """Enqueue n_steps into preallocated outputs (no synchronisation);
+        maps (optional) receives the discovery maps after every step."""
         for tns, shape in ((obs, (n_steps, self.obs_words)), (rew, (n_steps, self.agents)),
                            (done, (n_steps, self.n_envs))):
             if tns.device != self.device or not tns.is_contiguous() or tns.numel() < shape[0] * shape[1]:
                 raise ValueError("output tensor has the wrong device, layout or size")
+        mptr = self._map_ptr(maps, n_steps)
         aptr = None
         if actions is not None:
             if (actions.dtype != self.torch.int8 or actions.device != self.device
@@ -192,21 +214,25 @@ class HaseBatch:
                 raise ValueError("actions must be a contiguous int8 device tensor "
                                  "[n_steps][agents_total]")
             aptr = actions.data_ptr()
-        _check(load().hase_step(self._h, int(n_steps), aptr, obs.data_ptr(), rew.data_ptr(),
-                                done.data_ptr(), int(mode)))
+        _check(load().hase_step_maps(self._h, int(n_steps), aptr, obs.data_ptr(), rew.data_ptr(),
+                                     done.data_ptr(), mptr, int(mode)))
 
-    def prepare(self, obs, rew, done, n_steps: int, actions=None) -> None:
+    def prepare(self, obs, rew, done, n_steps: int, actions=None, maps=None) -> None:
         """Capture the persistent-step graph for these buffers without running it."""
         aptr = None if actions is None else actions.data_ptr()
-        _check(load().hase_prepare(self._h, int(n_steps), aptr, obs.data_ptr(), rew.data_ptr(),
-                                   done.data_ptr()))
+        _check(load().hase_prepare_maps(self._h, int(n_steps), aptr, obs.data_ptr(),
+                                        rew.data_ptr(), done.data_ptr(),
+                                        self._map_ptr(maps, n_steps)))
 
-    def step(self, n_steps: int = 1, actions=None, mode: int = PERSISTENT):
-        obs, rew, done = self.alloc_outputs(n_steps)
+    def step(self, n_steps: int = 1, actions=None, mode: int = PERSISTENT, maps: bool = False):
+        """(obs, rew, done) of n_steps, plus the discovery maps when maps."""
+        out = self.alloc_outputs(n_steps, maps)
         if actions is not None and not self.torch.is_tensor(actions):
             actions = self.torch.as_tensor(np.ascontiguousarray(actions, np.int8)).to(self.device)
-        self.step_into(obs, rew, done, n_steps, actions, mode)
-        return obs, rew, done
+        self.step_into(*out[:3], n_steps, actions, mode, out[3] if maps else None)
+        if maps:
+            return out[0], out[1], out[2], out[3][:, :self.map_words]
+        return out
 
     def observe(self):
         obs = self.torch.empty(self.obs_words, dtype=self.torch.int32, device=self.device)
@@ -218,9 +244,11 @@ class HaseBatch:
         st = dict(walls=np.zeros(self.cells, np.uint8), pos_x=np.zeros(self.agents, np.uint8),
                   pos_y=np.zeros(self.agents, np.uint8), found=np.zeros(self.n_envs, np.uint32),
                   t=np.zeros(self.n_envs, np.uint32), episode=np.zeros(self.n_envs, np.uint32),
-                  steps=np.zeros(self.n_envs, np.uint32), seed=np.zeros(self.n_envs, np.uint64))
+                  steps=np.zeros(self.n_envs, np.uint32), seed=np.zeros(self.n_envs, np.uint64),
+                  discovered=np.zeros(self.map_words, np.uint32))
         hs = HostState(*[st[k].ctypes.data for k in
-                         ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")])
+                         ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")],
+                       st["discovered"].ctypes.data if self.map_words else None)
         _check(load().hase_get_state(self._h, ctypes.byref(hs)))
         return st
 
@@ -235,8 +263,16 @@ class HaseBatch:
             if a.size != n:
                 raise ValueError(f"state field {k} has {a.size} entries, expected {n}")
             keep[k] = a
+        disc = None  # absent: every discovery map is cleared
+        if st.get("discovered") is not None and self.map_words:
+            keep["discovered"] = np.ascontiguousarray(st["discovered"], dtype=np.uint32).reshape(-1)
+            if keep["discovered"].size != self.map_words:
+                raise ValueError(f"state field discovered has {keep['discovered'].size} entries, "
+                                 f"expected {self.map_words}")
+            disc = keep["discovered"].ctypes.data
         hs = HostState(*[keep[k].ctypes.data for k in
-                         ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")])
+                         ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")],
+                       disc)
         _check(load().hase_set_state(self._h, ctypes.byref(hs)))
 
     def offsets(self):
@@ -244,6 +280,11 @@ class HaseBatch:
         ao = np.zeros(self.n_envs, np.uint64)
         _check(load().hase_get_offsets(self._h, oo.ctypes.data, ao.ctypes.data))
         return oo, ao
+
+    def map_offsets(self):
+        mo = np.zeros(self.n_envs, np.uint64)
+        _check(load().hase_get_map_offsets(self._h, mo.ctypes.data))
+        return mo
 
     def set_tiling(self, lanes) -> None:
         arr = (ctypes.c_uint32 * N_BUCKETS)(*[int(x) for x in lanes])
@@ -293,11 +334,14 @@ def multi_workspace_bytes(batches) -> int:
 
 def step_multi(items, n_steps: int, workspace, stream) -> None:
     """Enqueue one multi-batch step: items are (batch, steps, out_step0,
-    actions or None, obs, rew, done) with per-batch device tensors."""
+    actions or None, obs, rew, done[, maps]) with per-batch device tensors."""
     ios = (StepIO * max(1, len(items)))()
-    for i, (b, k, s0, act, obs, rew, done) in enumerate(items):
+    for i, it in enumerate(items):
+        b, k, s0, act, obs, rew, done = it[:7]
+        mp = it[7] if len(it) > 7 else None
         ios[i] = StepIO(b.handle.value, int(k), int(s0), None if act is None else act.data_ptr(),
-                        obs.data_ptr(), rew.data_ptr(), done.data_ptr())
+                        obs.data_ptr(), rew.data_ptr(), done.data_ptr(),
+                        None if mp is None else mp.data_ptr())
     _check(load().hase_step_multi(ios, len(items), int(n_steps), workspace.data_ptr(),
                                   workspace.numel() * workspace.element_size(),
                                   ctypes.c_void_p(stream.cuda_stream)))

@@ -10,6 +10,7 @@ iid-wall grids stand in for them. Named workloads:
   single1k     1024 envs, 32x32, 15% walls, 1 + 1, r=3 (7x7), C=3, 10k steps
   single16k    16384 envs, same as single1k
   los16k       single16k with line-of-sight occlusion in the windows (flag 8)
+  explore16k   single16k with exploration rewards and discovery maps (flag 16)
   multi10      4096 envs, 32x32, 15% walls, 5 + 5, r=4 (9x9), C=4, 2000 steps
   uneven8k     8192 per-env specs: side {16,32,64} w.p. (.5,.3,.2), n ~ U{1..10},
                walls ~ U{5..25}%, r ~ U{2,3,4}, C=4, 2000 steps
@@ -25,6 +26,7 @@ COLLIDE = 1
 CAPTURE_ENDS = 2
 DESYNC = 4
 OCCLUDE = 8  # line-of-sight occlusion in the windows
+EXPLORE = 16  # exploration rewards and per-env discovery maps
 DEFAULT_FLAGS = COLLIDE | CAPTURE_ENDS | DESYNC
 EPISODE_LEN = 256
 
@@ -44,6 +46,8 @@ WORKLOADS = {
     "single16k": dict(n_envs=16384, spec=spec(32, 32, 2, 3, 3, 15), steps=10000, seed=2),
     "los16k": dict(n_envs=16384, spec=spec(32, 32, 2, 3, 3, 15, flags=DEFAULT_FLAGS | OCCLUDE),
                    steps=10000, seed=2),
+    "explore16k": dict(n_envs=16384, spec=spec(32, 32, 2, 3, 3, 15, flags=DEFAULT_FLAGS | EXPLORE),
+                       steps=10000, seed=2),
     "multi10": dict(n_envs=4096, spec=spec(32, 32, 10, 4, 4, 15), steps=2000, seed=3),
     "uneven8k": dict(n_envs=8192, spec=None, steps=2000, seed=4, spec_seed=4),
 }

@@ -1167,10 +1167,19 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
                     for (uint32_t jw = 0; k < nsteps; ++k, ++jw) step((w >> (12u * jw)) & 0xfffull);
                 }
+            } else if constexpr (KIND == KIND_PLAIN) {
+                // one loop, the window drawn when its index wraps (measured
+                // faster than the nested form below for the plain loops)
+                uint64_t w = 0;
+                for (uint32_t k = 0; k < nsteps; ++k) {
+                    const uint32_t jw = k & (uint32_t)(LANES - 1);
+                    if (jw == 0u) w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+                    step((w >> (12u * jw)) & 0xfffull);
+                }
             } else {
-                // one window per outer iteration: a plain nested loop (a
-                // "draw when the window index wraps" test inside one loop
-                // let the compiler thread it into an irreducible loop)
+                // the feature loops: one window per outer iteration (with the
+                // single-loop form the compiler threaded the wrap test into
+                // an irreducible loop)
                 for (uint32_t left = nsteps; left != 0u;) {
                     const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
                     const uint32_t nw = left < (uint32_t)LANES ? left : (uint32_t)LANES;
@@ -1179,9 +1188,25 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     left -= nw;
                 }
             }
+        } else if constexpr (WINDOWED && KIND == KIND_PLAIN) {
+            // lane l draws block (step + wstep, group wgroup) of the window
+            uint32_t win = 0;
+            int j = 0;
+            for (uint32_t k = 0; k < nsteps; ++k) {
+                if (j == 0) win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                uint64_t acts = 0;
+#pragma unroll
+                for (int g = 0; g < MAXCALLS; ++g) {
+                    if (g < ncalls) {
+                        const uint32_t v = (uint32_t)__shfl((int)win, q * LANES + j * ncalls + g, 64);
+                        acts |= (uint64_t)v << (12 * g);
+                    }
+                }
+                step(acts);
+                j = (j + 1 == kb) ? 0 : j + 1;
+            }
         } else if constexpr (WINDOWED) {
-            // lane l draws block (step + wstep, group wgroup) of the window;
-            // one window of kb steps per outer iteration
+            // the same, one window of kb steps per outer iteration
             for (uint32_t left = nsteps; left != 0u;) {
                 const uint32_t win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
                 const uint32_t nw = left < (uint32_t)kb ? left : (uint32_t)kb;

@@ -101,7 +101,9 @@ def main(argv=None):
     import bench
     from paper_2604_27162_amd import workloads as wl
     specs = wl.workload_specs(args.workload)
-    alg = args.steps * bench.out_bytes_per_step(specs) + bench.state_bytes_per_launch(specs)
+    # bench.py writes the discovery maps of exploring workloads by default
+    maps = any(s["flags"] & bench.EXPLORE for s in specs)
+    alg = args.steps * bench.out_bytes_per_step(specs, maps) + bench.state_bytes_per_launch(specs)
     khash = bench.kernel_source_hash()
 
     tj = os.path.join(args.out, "traffic.json")

@@ -205,3 +205,40 @@ def test_step_multi_with_exploring_requests():
         if b.map_words:
             assert_maps(out[3][:, :b.map_words], oo[3])
         assert_state(b, ob)
+
+
+def test_full_size_explore16k_sampled():
+    """The benchmark's exploring workload at full size (16384 envs, persistent
+    launch with map output, default tiling), sampled envs against one-env
+    oracle runs (an env's trajectory depends only on its seed, id and spec)."""
+    from tests.test_gpu_parity import fbits, offsets
+
+    w = wl.WORKLOADS["explore16k"]
+    specs = wl.workload_specs("explore16k")
+    steps = 2000
+    print(f"case: full size explore16k, {len(specs)} envs x {steps} steps", flush=True)
+    g = hase.HaseBatch(specs, device=DEV)
+    g.reset(w["seed"])
+    go, gr, gd, gm = g.step(steps, maps=True)
+    torch.cuda.synchronize()
+    obs_off, agent_off = offsets(specs)
+    map_off = g.map_offsets()
+    rng = np.random.Generator(np.random.PCG64(2))
+    sample = sorted(set([0, len(specs) - 1] + list(rng.choice(len(specs), 24, replace=False))))
+    for e in sample:
+        s = specs[e]
+        nw = s["n"] * s["C"] * (((2 * s["r"] + 1) ** 2 + 31) // 32)
+        mw = s["H"] * ((s["W"] + 31) // 32)
+        one = o.OracleBatch([s], env_ids=[e])
+        one.reset(w["seed"])
+        oo, orr, od, om = one.step(steps, maps=True)
+        np.testing.assert_array_equal(u32(go[:, obs_off[e]:obs_off[e] + nw]), oo,
+                                      err_msg=f"obs env {e}")
+        np.testing.assert_array_equal(fbits(gr[:, agent_off[e]:agent_off[e] + s["n"]]),
+                                      orr.view(np.uint32), err_msg=f"rew env {e}")
+        np.testing.assert_array_equal(gd[:, e].cpu().numpy(), od[:, 0], err_msg=f"done env {e}")
+        np.testing.assert_array_equal(u32(gm[:, int(map_off[e]):int(map_off[e]) + mw]), om,
+                                      err_msg=f"maps env {e}")
+    g.close()
+    del go, gr, gd, gm
+    torch.cuda.empty_cache()

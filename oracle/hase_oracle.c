@@ -41,16 +41,35 @@
 #define OR_DESYNC 4u
 #define OR_OCCLUDE 8u
 #define OR_EXPLORE 16u
+#define OR_TERRAIN 32u
 
 #define OR_STREAM_ACTION 0u
 #define OR_STREAM_SPAWN 1u
 #define OR_STREAM_WALL 2u
 #define OR_STREAM_DESYNC 3u
+#define OR_STREAM_MOVE 4u
 
 #define OR_SPAWN_ATTEMPTS 64
 
-/* Field order of one row of the int32 spec table [n_envs][9]. */
-enum { SP_H = 0, SP_W, SP_N, SP_S, SP_R, SP_C, SP_WALLPCT, SP_FLAGS, SP_L, SP_FIELDS };
+/* Field order of one row of the int32 spec table [n_envs][SP_FIELDS]. The
+ * terrain fields (OR_TERRAIN): percent of water and mud cells, percent chance
+ * that a walker entering mud gets stuck, percent chance that a move attempt
+ * onto a tile succeeds per (agent class, tile) -- walker, swimmer, flyer x
+ * ground, water, mud --, and the agent classes, 2 bits per agent (0 walker,
+ * 1 swimmer, 2 flyer), agents 0..15 in CLS_LO and 16..19 in CLS_HI. */
+enum {
+    SP_H = 0, SP_W, SP_N, SP_S, SP_R, SP_C, SP_WALLPCT, SP_FLAGS, SP_L,
+    SP_WATERPCT, SP_MUDPCT, SP_STUCKPCT, SP_SPEED, SP_CLS_LO = SP_SPEED + 9, SP_CLS_HI,
+    SP_FIELDS
+};
+
+/* Tile types (cells of the walls array; without OR_TERRAIN only 0 and 1)
+ * and agent classes (reading R28 of the traversal kinetics of Sec. 3.2 and
+ * the tile / agent flags of Fig. "Bit Packing Environment Structure"):
+ * ground is walkable and flyable, water aquatic and flyable, mud walkable
+ * and flyable but sticky for walkers, walls block everyone. */
+enum { OR_GROUND = 0, OR_WALL = 1, OR_WATER = 2, OR_MUD = 3 };
+enum { OR_WALKER = 0, OR_SWIMMER = 1, OR_FLYER = 2 };
 
 typedef struct {
     int32_t n_envs;
@@ -68,6 +87,7 @@ typedef struct {
     const int64_t *disc_off;  /* [n_envs] first discovery-map word of env e */
     int64_t disc_total;       /* sum of map words over envs */
     uint32_t *disc;           /* [disc_total] discovery maps (OR_EXPLORE envs) */
+    uint32_t *stuck;          /* [n_envs] bit i: agent i is stuck (OR_TERRAIN envs) */
 } or_batch;
 
 /* ---------------------------------------------------------------- Philox */
@@ -143,6 +163,32 @@ static int or_in_bounds(int x, int y, int W, int H)
     return x >= 0 && x < W && y >= 0 && y < H;
 }
 
+/* Class of agent i (every agent is a walker without OR_TERRAIN). */
+static int or_class(const int32_t *sp, int i)
+{
+    if (!((uint32_t)sp[SP_FLAGS] & OR_TERRAIN)) return OR_WALKER;
+    uint32_t w = (uint32_t)(i < 16 ? sp[SP_CLS_LO] : sp[SP_CLS_HI]);
+    return (int)((w >> (2 * (i & 15))) & 3u);
+}
+
+/* May an agent of class cls stand on a tile of this type? */
+static int or_enterable(int type, int cls)
+{
+    switch (type) {
+    case OR_GROUND: return cls == OR_WALKER || cls == OR_FLYER;
+    case OR_WATER: return cls == OR_SWIMMER || cls == OR_FLYER;
+    case OR_MUD: return cls == OR_WALKER || cls == OR_FLYER;
+    default: return 0;
+    }
+}
+
+/* Does a uniform 32-bit word x fall below pct percent: x / 2^32 < pct / 100,
+ * exactly (pct in 0..100). */
+static int or_chance(uint32_t x, int pct)
+{
+    return (uint64_t)x * 100u < ((uint64_t)(uint32_t)pct << 32);
+}
+
 /* ----------------------------------------------------------- line of sight */
 
 /* Does the open segment from the centre of cell (0,0) to the centre of cell
@@ -205,7 +251,7 @@ static int or_visible(const int32_t *sp, const uint8_t *walls, int ax, int ay, i
         for (int ex = x0; ex <= x1; ++ex) {
             if ((ex == 0 && ey == 0) || (ex == dx && ey == dy)) continue;
             int bx = ax + ex, by = ay + ey;
-            int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx];
+            int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx] == OR_WALL;
             if (blocking && or_segment_crosses(dx, dy, ex, ey)) return 0;
         }
     }
@@ -214,22 +260,23 @@ static int or_visible(const int32_t *sp, const uint8_t *walls, int ax, int ay, i
 
 /* Agent spawn for episode `e` (reading: agents are placed one after another
  * in index order; agent i tries up to 64 uniformly drawn cells and takes the
- * first that is neither a wall nor held by an agent < i; if all 64 draws fail
- * it takes the first acceptable cell scanning row-major from the cell after
- * the last draw, wrapping around). The grid itself is never touched: the
- * pristine grid of Sec. 4.2 is the one drawn at reset. */
+ * first that its class may stand on (without OR_TERRAIN: not a wall) and no
+ * agent < i holds; if all 64 draws fail it takes the first acceptable cell
+ * scanning row-major from the cell after the last draw, wrapping around).
+ * The grid itself is never touched: the pristine grid of Sec. 4.2 is the one
+ * drawn at reset. */
 static void or_spawn(const int32_t *sp, const uint8_t *walls, uint8_t *px, uint8_t *py,
                      uint64_t seed, uint32_t env, uint32_t e)
 {
     int H = sp[SP_H], W = sp[SP_W], n = sp[SP_N];
     uint32_t cells = (uint32_t)(H * W);
     for (int i = 0; i < n; ++i) {
-        int placed = 0;
+        int placed = 0, cls = or_class(sp, i);
         uint32_t c = 0;
         for (int j = 0; j < OR_SPAWN_ATTEMPTS && !placed; ++j) {
             c = or_range(or_draw(seed, env, OR_STREAM_SPAWN, (uint32_t)i, e, (uint32_t)j, 0), cells);
             int x = (int)(c % (uint32_t)W), y = (int)(c / (uint32_t)W);
-            int ok = !walls[c];
+            int ok = or_enterable(walls[c], cls);
             for (int k = 0; k < i && ok; ++k)
                 if (px[k] == x && py[k] == y) ok = 0;
             if (ok) { px[i] = (uint8_t)x; py[i] = (uint8_t)y; placed = 1; }
@@ -237,7 +284,7 @@ static void or_spawn(const int32_t *sp, const uint8_t *walls, uint8_t *px, uint8
         for (uint32_t d = 1; d <= cells && !placed; ++d) {
             uint32_t cc = (c + d) % cells;
             int x = (int)(cc % (uint32_t)W), y = (int)(cc / (uint32_t)W);
-            int ok = !walls[cc];
+            int ok = or_enterable(walls[cc], cls);
             for (int k = 0; k < i && ok; ++k)
                 if (px[k] == x && py[k] == y) ok = 0;
             if (ok) { px[i] = (uint8_t)x; py[i] = (uint8_t)y; placed = 1; }
@@ -248,10 +295,11 @@ static void or_spawn(const int32_t *sp, const uint8_t *walls, uint8_t *px, uint8
 /* Decentralised observation of every agent (observability mode 1, Sec. 3.3):
  * the (2r+1)x(2r+1) window around the agent, one bit per window cell, bit
  * k = (dy+r)*(2r+1) + (dx+r), packed LSB-first into ceil((2r+1)^2/32) words
- * per channel. Channels: 0 blocking tile or outside the map, 1 teammate
- * (another agent of the same role), 2 opponent, 3 (only when C = 4) outside
- * the map. Layout [agent][channel][word]. With OR_OCCLUDE, a window cell not
- * visible from the agent (or_visible) reads 0 in every channel. */
+ * per channel. Channels: 0 blocking tile or outside the map (with
+ * OR_TERRAIN: a tile the agent's class may not enter, or outside), 1
+ * teammate (another agent of the same role), 2 opponent, 3 (only when C = 4)
+ * outside the map. Layout [agent][channel][word]. With OR_OCCLUDE, a window
+ * cell not visible from the agent (or_visible) reads 0 in every channel. */
 static void or_observe(const int32_t *sp, const uint8_t *walls, const uint8_t *px,
                        const uint8_t *py, uint32_t *obs)
 {
@@ -261,6 +309,7 @@ static void or_observe(const int32_t *sp, const uint8_t *walls, const uint8_t *p
     memset(obs, 0, sizeof(uint32_t) * (size_t)(n * C * w));
     for (int i = 0; i < n; ++i) {
         uint32_t *oi = obs + (size_t)i * C * w;
+        int cls = or_class(sp, i);
         for (int dy = -r; dy <= r; ++dy) {
             for (int dx = -r; dx <= r; ++dx) {
                 int k = (dy + r) * d + (dx + r);
@@ -269,7 +318,7 @@ static void or_observe(const int32_t *sp, const uint8_t *walls, const uint8_t *p
                 int inb = or_in_bounds(cx, cy, W, H);
                 uint32_t bit = 1u << (k & 31);
                 int word = k >> 5;
-                if (!inb || walls[cy * W + cx]) oi[0 * w + word] |= bit;
+                if (!inb || !or_enterable(walls[cy * W + cx], cls)) oi[0 * w + word] |= bit;
                 if (inb) {
                     for (int j = 0; j < n; ++j) {
                         if (j == i || px[j] != cx || py[j] != cy) continue;
@@ -287,13 +336,17 @@ static void or_observe(const int32_t *sp, const uint8_t *walls, const uint8_t *p
 
 /* ---------------------------------------------------------------- reset */
 
-/* reset(seed) of every env: draw the iid walls, check there are at least n
- * free cells, clear the counters, spawn episode 0, draw the desynchronising
- * initial elapsed time t0 (reading of Sec. 3.3: instead of stepping each env a
- * random number of times, its first episode starts with t0 ~ U{0..L-1} steps
- * already elapsed), and write the episode's first observation into obs0.
- * Returns 0, or -(1 + e) for the first env e with fewer free cells than
- * agents. */
+/* reset(seed) of every env: draw the iid walls (with OR_TERRAIN the tile
+ * types: the same word per cell is a wall below the wall threshold, else
+ * water below the threshold of wall + water percent, else mud below that of
+ * wall + water + mud percent, else ground), check there are enough free
+ * cells (at least n; with OR_TERRAIN at least n cells that each class
+ * present among the agents may stand on), clear the counters, spawn episode
+ * 0, draw the desynchronising initial elapsed time t0 (reading of Sec. 3.3:
+ * instead of stepping each env a random number of times, its first episode
+ * starts with t0 ~ U{0..L-1} steps already elapsed), and write the episode's
+ * first observation into obs0. Returns 0, or -(1 + e) for the first env e
+ * without enough free cells. */
 int or_reset(or_batch *b, uint64_t seed, uint32_t *obs0)
 {
     for (int e = 0; e < b->n_envs; ++e) {
@@ -302,18 +355,26 @@ int or_reset(or_batch *b, uint64_t seed, uint32_t *obs0)
         uint8_t *walls = b->walls + b->grid_off[e];
         uint8_t *px = b->px + b->agent_off[e], *py = b->py + b->agent_off[e];
         uint32_t env = b->env_id[e];
+        int terrain = ((uint32_t)sp[SP_FLAGS] & OR_TERRAIN) != 0;
         uint32_t T = or_wall_threshold((uint32_t)sp[SP_WALLPCT]);
-        int free_cells = 0;
+        uint32_t Tw = or_wall_threshold((uint32_t)(sp[SP_WALLPCT] + sp[SP_WATERPCT]));
+        uint32_t Tm = or_wall_threshold((uint32_t)(sp[SP_WALLPCT] + sp[SP_WATERPCT] + sp[SP_MUDPCT]));
         b->seed[e] = seed;
         for (int c = 0; c < H * W; ++c) {
             uint32_t x = or_draw(seed, env, OR_STREAM_WALL, (uint32_t)(c >> 2), 0, 0, c & 3);
-            walls[c] = (uint8_t)(x < T);
-            free_cells += !walls[c];
+            uint8_t type = x < T ? OR_WALL : OR_GROUND;
+            if (terrain && type == OR_GROUND) type = x < Tw ? OR_WATER : (x < Tm ? OR_MUD : OR_GROUND);
+            walls[c] = type;
         }
-        if (free_cells < n) return -(1 + e);
+        for (int i = 0; i < n; ++i) {
+            int cls = or_class(sp, i), room = 0;
+            for (int c = 0; c < H * W; ++c) room += or_enterable(walls[c], cls);
+            if (room < n) return -(1 + e);
+        }
         b->steps[e] = 0;
         b->ep[e] = 0;
         b->found[e] = 0;
+        b->stuck[e] = 0;
         if ((uint32_t)sp[SP_FLAGS] & OR_EXPLORE)
             memset(b->disc + b->disc_off[e], 0, sizeof(uint32_t) * (size_t)(H * or_map_row_words(W)));
         or_spawn(sp, walls, px, py, seed, env, 0);
@@ -347,6 +408,11 @@ static const int OR_DY[5] = { 0, -1, 1, 0, 0 };
  *   2 moves in agent-index order; a move is rejected if it leaves the map,
  *     enters a blocking tile, or (collisions on) enters a cell held by any
  *     other agent at that moment (agents < i already moved, agents > i not);
+ *     with OR_TERRAIN (reading R28) a stuck agent does not move, a tile its
+ *     class may not enter blocks it, and an allowed move succeeds with the
+ *     (class, tile) move chance; a walker that enters mud gets stuck with
+ *     the stuck chance; then every stuck agent with a teammate that is not
+ *     stuck within Chebyshev distance 1 is freed (rescue, Sec. 3.2);
  *   3 detection: seeker i sees hider h iff their Chebyshev distance is <= r
  *     (and, with OR_OCCLUDE, h's cell is visible from i's, or_visible);
  *     seeker reward = hiders seen, hider reward = -(seekers seeing it)
@@ -355,8 +421,8 @@ static const int OR_DY[5] = { 0, -1, 1, 0, 0 };
  *   4 t += 1; terminated = capture rule on, at least one hider, every hider
  *     found; truncated = t >= L; done = terminated | truncated << 1;
  *   3b exploration reward and discovery map (OR_EXPLORE);
- *   5 if done: next episode, t = 0, Found cleared, agents respawned, grid kept,
- *     discovery map cleared;
+ *   5 if done: next episode, t = 0, Found and stuck cleared, agents respawned,
+ *     grid kept, discovery map cleared;
  *   6 step count += 1;
  *   7 observation of the (possibly new) state.
  */
@@ -384,18 +450,48 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
     }
 
     /* 2 moves */
+    int terrain = (flags & OR_TERRAIN) != 0;
     for (int i = 0; i < n; ++i) {
         if (a[i] == 0) continue;
+        if (terrain && (b->stuck[e] >> i) & 1u) continue;
         int tx = px[i] + OR_DX[a[i]], ty = py[i] + OR_DY[a[i]];
         if (!or_in_bounds(tx, ty, W, H)) continue;
-        if (walls[ty * W + tx]) continue;
+        int type = walls[ty * W + tx], cls = or_class(sp, i);
+        if (!or_enterable(type, cls)) continue;
         int blocked = 0;
         if (flags & OR_COLLIDE)
             for (int j = 0; j < n; ++j)
                 if (j != i && px[j] == tx && py[j] == ty) blocked = 1;
         if (blocked) continue;
+        if (terrain) {
+            /* move and stuck draws: words 2(i&1) and 2(i&1)+1 of the MOVE
+             * block of agent pair i>>1 at this step count */
+            uint32_t u = or_draw(seed, env, OR_STREAM_MOVE, (uint32_t)(i >> 1), b->steps[e], 0,
+                                 2 * (i & 1));
+            int tile = type == OR_GROUND ? 0 : (type == OR_WATER ? 1 : 2);
+            if (!or_chance(u, sp[SP_SPEED + 3 * cls + tile])) continue;
+            if (cls == OR_WALKER && type == OR_MUD) {
+                uint32_t v = or_draw(seed, env, OR_STREAM_MOVE, (uint32_t)(i >> 1), b->steps[e], 0,
+                                     2 * (i & 1) + 1);
+                if (or_chance(v, sp[SP_STUCKPCT])) b->stuck[e] |= 1u << i;
+            }
+        }
         px[i] = (uint8_t)tx;
         py[i] = (uint8_t)ty;
+    }
+    if (terrain) {
+        /* rescue: freed by a teammate that is not stuck, at Chebyshev
+         * distance <= 1, after the moves */
+        uint32_t before = b->stuck[e];
+        for (int i = 0; i < n; ++i) {
+            if (!((before >> i) & 1u)) continue;
+            for (int j = 0; j < n; ++j) {
+                if (j == i || ((before >> j) & 1u)) continue;
+                if (or_is_seeker(j, S) != or_is_seeker(i, S)) continue;
+                int ddx = px[i] - px[j], ddy = py[i] - py[j];
+                if (ddx >= -1 && ddx <= 1 && ddy >= -1 && ddy <= 1) b->stuck[e] &= ~(1u << i);
+            }
+        }
     }
 
     /* 3 detection and rewards */
@@ -469,6 +565,7 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
         b->ep[e] += 1;
         b->t[e] = 0;
         b->found[e] = 0;
+        b->stuck[e] = 0;
         if (flags & OR_EXPLORE)
             memset(b->disc + b->disc_off[e], 0, sizeof(uint32_t) * (size_t)(H * or_map_row_words(W)));
         or_spawn(sp, walls, px, py, seed, env, b->ep[e]);

@@ -23,7 +23,24 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hase_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-SPEC_FIELDS = ("H", "W", "n", "S", "r", "C", "wall_pct", "flags", "L")
+SPEC_FIELDS = ("H", "W", "n", "S", "r", "C", "wall_pct", "flags", "L", "water_pct", "mud_pct",
+               "stuck_pct") + tuple(f"speed{k}" for k in range(9)) + ("classes_lo", "classes_hi")
+# terrain fields (flag 32) of a spec dict and their values when absent:
+# speed = move chances in percent, walker / swimmer / flyer x ground / water /
+# mud; classes = 2 bits per agent (0 walker, 1 swimmer, 2 flyer)
+TERRAIN_DEFAULTS = dict(water_pct=0, mud_pct=0, stuck_pct=0, speed=(100,) * 9, classes=0)
+
+
+def spec_row(s: dict) -> list:
+    """One int32 row of the spec table from a spec dict."""
+    t = {k: s.get(k, v) for k, v in TERRAIN_DEFAULTS.items()}
+    speed = [int(v) for v in t["speed"]]
+    if len(speed) != 9:
+        raise ValueError("speed needs 9 entries (3 classes x 3 tiles)")
+    cls = int(t["classes"])
+    return ([int(s[f]) for f in SPEC_FIELDS[:9]] +
+            [int(t["water_pct"]), int(t["mud_pct"]), int(t["stuck_pct"])] + speed +
+            [np.int32(np.uint32(cls & 0xffffffff)), np.int32(np.uint32(cls >> 32))])
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +74,7 @@ class _Batch(ctypes.Structure):
         ("disc_off", ctypes.c_void_p),
         ("disc_total", ctypes.c_int64),
         ("disc", ctypes.c_void_p),
+        ("stuck", ctypes.c_void_p),
     ]
 
 
@@ -119,10 +137,11 @@ def words_per_channel(r: int) -> int:
 
 
 def spec_table(specs) -> np.ndarray:
-    """int32 [n_envs][9] from a sequence of dicts, or an int32 table as is."""
+    """int32 [n_envs][len(SPEC_FIELDS)] from a sequence of dicts, or an int32
+    table as is."""
     if isinstance(specs, np.ndarray):
         return np.ascontiguousarray(specs, dtype=np.int32).reshape(-1, len(SPEC_FIELDS))
-    rows = [[int(s[f]) for f in SPEC_FIELDS] for s in specs]
+    rows = [spec_row(s) for s in specs]
     return np.ascontiguousarray(np.array(rows, dtype=np.int32).reshape(-1, len(SPEC_FIELDS)))
 
 
@@ -168,6 +187,7 @@ class OracleBatch:
         self.ep = np.zeros(ne, np.uint32)
         self.steps = np.zeros(ne, np.uint32)
         self.seed = np.zeros(ne, np.uint64)
+        self.stuck = np.zeros(ne, np.uint32)
         if env_ids is None:
             self.env_id = (np.arange(ne, dtype=np.uint64) + env_id_base).astype(np.uint32)
         else:
@@ -178,13 +198,14 @@ class OracleBatch:
             self.walls.ctypes.data, self.px.ctypes.data, self.py.ctypes.data,
             self.found.ctypes.data, self.t.ctypes.data, self.ep.ctypes.data,
             self.steps.ctypes.data, self.seed.ctypes.data, self.env_id.ctypes.data,
-            self.disc_off.ctypes.data, self.disc_total, self.disc.ctypes.data)
+            self.disc_off.ctypes.data, self.disc_total, self.disc.ctypes.data,
+            self.stuck.ctypes.data)
 
     def reset(self, seed: int) -> np.ndarray:
         obs0 = np.zeros(self.obs_total, np.uint32)
         rc = self._lib.or_reset(ctypes.byref(self._c), ctypes.c_uint64(seed), obs0.ctypes.data)
         if rc != 0:
-            raise ValueError(f"env {-rc - 1} has fewer free cells than agents")
+            raise ValueError(f"env {-rc - 1} has too few free cells for its agents")
         return obs0
 
     def step(self, n_steps: int = 1, actions=None, maps: bool = False):
@@ -213,7 +234,7 @@ class OracleBatch:
         return dict(walls=self.walls.copy(), pos_x=self.px.copy(), pos_y=self.py.copy(),
                     found=self.found.copy(), t=self.t.copy(), episode=self.ep.copy(),
                     steps=self.steps.copy(), seed=self.seed.copy(), env_id=self.env_id.copy(),
-                    discovered=self.disc[:self.disc_total].copy())
+                    discovered=self.disc[:self.disc_total].copy(), stuck=self.stuck.copy())
 
     def set_state(self, st: dict) -> None:
         self.walls[:] = st["walls"]
@@ -227,6 +248,8 @@ class OracleBatch:
         self.env_id[:] = st["env_id"]
         if "discovered" in st:  # optional: exploring envs' discovery maps
             self.disc[:self.disc_total] = st["discovered"]
+        if "stuck" in st:  # optional: stuck agents of terrain envs
+            self.stuck[:] = st["stuck"]
 
 
 def spawn(spec: dict, walls: np.ndarray, seed: int, env: int, episode: int):

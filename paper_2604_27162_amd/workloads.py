@@ -11,6 +11,9 @@ iid-wall grids stand in for them. Named workloads:
   single16k    16384 envs, same as single1k
   los16k       single16k with line-of-sight occlusion in the windows (flag 8)
   explore16k   single16k with exploration rewards and discovery maps (flag 16)
+  terrain4k    4096 envs, 32x32, 10% walls, 15% water, 10% mud, 5 + 5 agents of
+               cycling classes (walker, swimmer, flyer), r=4, C=4, 2000 steps
+               (flag 32)
   multi10      4096 envs, 32x32, 15% walls, 5 + 5, r=4 (9x9), C=4, 2000 steps
   uneven8k     8192 per-env specs: side {16,32,64} w.p. (.5,.3,.2), n ~ U{1..10},
                walls ~ U{5..25}%, r ~ U{2,3,4}, C=4, 2000 steps
@@ -27,6 +30,8 @@ CAPTURE_ENDS = 2
 DESYNC = 4
 OCCLUDE = 8  # line-of-sight occlusion in the windows
 EXPLORE = 16  # exploration rewards and per-env discovery maps
+TERRAIN = 32  # tile types, agent classes, move chances, stuck and rescue
+WALKER, SWIMMER, FLYER = 0, 1, 2
 DEFAULT_FLAGS = COLLIDE | CAPTURE_ENDS | DESYNC
 EPISODE_LEN = 256
 
@@ -40,6 +45,27 @@ def spec(H, W, n, r, C, wall_pct, S=None, flags=DEFAULT_FLAGS, L=EPISODE_LEN) ->
                 wall_pct=int(wall_pct), flags=int(flags), L=int(L))
 
 
+def classes_word(classes) -> int:
+    """Pack per-agent classes (WALKER, SWIMMER, FLYER) 2 bits per agent."""
+    w = 0
+    for i, c in enumerate(classes):
+        w |= int(c) << (2 * i)
+    return w
+
+
+def with_terrain(s: dict, water_pct=15, mud_pct=10, stuck_pct=25, speed=None, classes=None) -> dict:
+    """A copy of spec s with terrain on: tile percentages, the stuck chance,
+    move chances (percent, walker / swimmer / flyer x ground / water / mud)
+    and agent classes (default: cycling walker, swimmer, flyer)."""
+    if speed is None:
+        speed = (100, 0, 60, 0, 100, 0, 80, 80, 80)
+    if classes is None:
+        classes = [i % 3 for i in range(s["n"])]
+    return dict(s, flags=s["flags"] | TERRAIN, water_pct=int(water_pct), mud_pct=int(mud_pct),
+                stuck_pct=int(stuck_pct), speed=tuple(int(v) for v in speed),
+                classes=classes_word(classes))
+
+
 WORKLOADS = {
     "small": dict(n_envs=1024, spec=spec(16, 16, 2, 2, 3, 10), steps=256, seed=1),
     "single1k": dict(n_envs=1024, spec=spec(32, 32, 2, 3, 3, 15), steps=10000, seed=2),
@@ -50,6 +76,8 @@ WORKLOADS = {
                        steps=10000, seed=2),
     "multi10": dict(n_envs=4096, spec=spec(32, 32, 10, 4, 4, 15), steps=2000, seed=3),
     "uneven8k": dict(n_envs=8192, spec=None, steps=2000, seed=4, spec_seed=4),
+    "terrain4k": dict(n_envs=4096, spec=with_terrain(spec(32, 32, 10, 4, 4, 10)), steps=2000,
+                      seed=5),
 }
 
 

@@ -44,7 +44,7 @@ def check_invariants(table, prev, new, obs, rew, done, envs=None):
     ne = table.shape[0]
     envs = range(ne) if envs is None else envs
     for e in envs:
-        H, W, n, S, r, C, _, flags, L = (int(v) for v in table[e])
+        H, W, n, S, r, C, _, flags, L = (int(v) for v in table[e][:9])
         d = 2 * r + 1
         w = int(wv[e])
         walls = new["walls"][goff[e]:goff[e] + H * W].reshape(H, W)

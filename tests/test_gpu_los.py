@@ -57,7 +57,7 @@ def test_occluded_bruteforce(family):
     flat = bf.flat_state(st)
     g = hase.HaseBatch([spec] * B, device=DEV)
     g.set_state(flat)
-    ob = o.OracleBatch(np.tile(np.array([[spec[f] for f in o.SPEC_FIELDS]], np.int32), (B, 1)))
+    ob = o.OracleBatch(np.tile(o.spec_table([spec]), (B, 1)))
     ob.set_state(flat)
     np.testing.assert_array_equal(u32(g.observe()), ob.observe(), err_msg="observe")
     gout = g.step(1, actions=acts.reshape(1, -1))

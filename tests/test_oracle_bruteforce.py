@@ -9,7 +9,7 @@ from tests import bruteforce_spec as bf
 
 def run_oracle(spec, st, acts):
     B = st["pos_x"].shape[0]
-    table = np.tile(np.array([[spec[f] for f in o.SPEC_FIELDS]], np.int32), (B, 1))
+    table = np.tile(o.spec_table([spec]), (B, 1))
     b = o.OracleBatch(table)
     b.set_state(bf.flat_state(st))
     obs, rew, done = b.step(1, actions=acts.reshape(1, -1))

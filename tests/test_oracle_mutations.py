@@ -13,6 +13,7 @@ from tests import bruteforce_spec as bf
 from tests import test_oracle_explore as explore
 from tests import test_oracle_golden as golden
 from tests import test_oracle_rng as rng
+from tests import test_oracle_terrain as terrain
 
 SRC = open(o.SRC).read()
 
@@ -24,11 +25,13 @@ MUTATIONS = {
     "window_bit_transposed": ("int k = (dy + r) * d + (dx + r);", "int k = (dx + r) * d + (dy + r);"),
     "hider_reward_sign": ("int v = or_is_seeker(i, S) ? count[i] : -count[i];", "int v = count[i];"),
     "truncation_off_by_one": ("int truncated = b->t[e] >= L;", "int truncated = b->t[e] > L;"),
-    "wall_index_transposed": ("if (walls[ty * W + tx]) continue;", "if (walls[tx * H + ty]) continue;"),
+    "wall_index_transposed": ("int type = walls[ty * W + tx], cls = or_class(sp, i);",
+                              "int type = walls[tx * H + ty], cls = or_class(sp, i);"),
     "philox_weyl_constant": ("k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
     "philox_key_word": ("uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi1 ^ c1 ^ k1;"),
-    "wall_channel_drops_outside": ("if (!inb || walls[cy * W + cx]) oi[0 * w + word] |= bit;",
-                                   "if (inb && walls[cy * W + cx]) oi[0 * w + word] |= bit;"),
+    "wall_channel_drops_outside": (
+        "if (!inb || !or_enterable(walls[cy * W + cx], cls)) oi[0 * w + word] |= bit;",
+        "if (inb && !or_enterable(walls[cy * W + cx], cls)) oi[0 * w + word] |= bit;"),
     "found_not_latched": ("b->found[e] |= 1u << h;", "b->found[e] = 1u << h;"),
     "respawn_old_episode": ("or_spawn(sp, walls, px, py, seed, env, b->ep[e]);",
                             "or_spawn(sp, walls, px, py, seed, env, b->ep[e] - 1);"),
@@ -42,13 +45,14 @@ MUTATIONS = {
                                  "if (ex == 0 && ey == 0) continue;"),
     "los_negative_direction_interval": ("lo->num = -(2 * e + 1); lo->den = -2 * d;",
                                         "lo->num = -(2 * e - 1); lo->den = -2 * d;"),
-    "los_outside_not_blocking": ("int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx];",
-                                 "int blocking = or_in_bounds(bx, by, W, H) && walls[by * W + bx];"),
+    "los_outside_not_blocking": (
+        "int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx] == OR_WALL;",
+        "int blocking = or_in_bounds(bx, by, W, H) && walls[by * W + bx] == OR_WALL;"),
     "explore_counted_after_update": ("if (pass == 0) {", "if (pass == 1) {"),
     "hiders_explore": ("for (int i = 0; i < S && i < n; ++i) {", "for (int i = 0; i < n; ++i) {"),
     "explore_map_kept_at_auto_reset": (
-        "        b->found[e] = 0;\n        if (flags & OR_EXPLORE)\n            memset(",
-        "        b->found[e] = 0;\n        if (0)\n            memset("),
+        "        b->stuck[e] = 0;\n        if (flags & OR_EXPLORE)\n            memset(",
+        "        b->stuck[e] = 0;\n        if (0)\n            memset("),
     "explore_ignores_occlusion": (
         "if ((flags & OR_OCCLUDE) && !or_visible(sp, walls, px[i], py[i], cx, cy))\n                            continue;",
         "if (0)\n                            continue;"),
@@ -56,6 +60,32 @@ MUTATIONS = {
     "detection_ignores_los": (
         "int vis = !(flags & OR_OCCLUDE) || or_visible(sp, walls, px[i], py[i], px[h], py[h]);",
         "int vis = 1;"),
+    "terrain_stuck_agent_moves": ("if (terrain && (b->stuck[e] >> i) & 1u) continue;", "if (0) continue;"),
+    "terrain_speed_ignored": ("if (!or_chance(u, sp[SP_SPEED + 3 * cls + tile])) continue;",
+                              "if (0) continue;"),
+    "terrain_speed_tile_swapped": ("int tile = type == OR_GROUND ? 0 : (type == OR_WATER ? 1 : 2);",
+                                   "int tile = type == OR_GROUND ? 0 : (type == OR_WATER ? 2 : 1);"),
+    "terrain_swimmer_on_ground": ("case OR_GROUND: return cls == OR_WALKER || cls == OR_FLYER;",
+                                  "case OR_GROUND: return 1;"),
+    "terrain_flyer_gets_stuck": ("if (cls == OR_WALKER && type == OR_MUD) {", "if (type == OR_MUD) {"),
+    "terrain_stuck_same_word": ("                                     2 * (i & 1) + 1);",
+                                "                                     2 * (i & 1));"),
+    "terrain_rescue_by_opponent": ("if (or_is_seeker(j, S) != or_is_seeker(i, S)) continue;",
+                                   "if (0) continue;"),
+    "terrain_rescue_by_stuck": ("if (j == i || ((before >> j) & 1u)) continue;",
+                                "if (j == i) continue;"),
+    "terrain_never_rescued": (
+        "if (ddx >= -1 && ddx <= 1 && ddy >= -1 && ddy <= 1) b->stuck[e] &= ~(1u << i);",
+        "if (0) b->stuck[e] &= ~(1u << i);"),
+    "terrain_water_mud_swapped": (
+        "type = x < Tw ? OR_WATER : (x < Tm ? OR_MUD : OR_GROUND);",
+        "type = x < Tw ? OR_MUD : (x < Tm ? OR_WATER : OR_GROUND);"),
+    "terrain_obs_ignores_class": (
+        "if (!inb || !or_enterable(walls[cy * W + cx], cls)) oi[0 * w + word] |= bit;",
+        "if (!inb || walls[cy * W + cx] == OR_WALL) oi[0 * w + word] |= bit;"),
+    "terrain_stuck_kept_at_auto_reset": (
+        "        b->found[e] = 0;\n        b->stuck[e] = 0;\n        if (flags & OR_EXPLORE)",
+        "        b->found[e] = 0;\n        if (flags & OR_EXPLORE)"),
 }
 
 
@@ -87,7 +117,7 @@ def run_pins(libpath, rocrand_philox):
                 bf.case_seeker_hider(n_patterns=12, r=3, C=4, flags=8 | 1, seed=8)]
         for spec, st, acts in fams:
             B = st["pos_x"].shape[0]
-            table = np.tile(np.array([[spec[f] for f in o.SPEC_FIELDS]], np.int32), (B, 1))
+            table = np.tile(o.spec_table([spec]), (B, 1))
             b = o.OracleBatch(table, libpath=libpath)
             b.set_state(bf.flat_state(st))
             obs, rew, done = b.step(1, actions=acts.reshape(1, -1))
@@ -110,7 +140,13 @@ def run_pins(libpath, rocrand_philox):
             ("explore_golden", lambda: explore.check_hand_worked(libpath)),
             ("explore_restated", lambda: explore.check_restated(False, libpath, n_envs=6, steps=60)),
             ("explore_restated_occluded",
-             lambda: explore.check_restated(True, libpath, n_envs=6, steps=60))]
+             lambda: explore.check_restated(True, libpath, n_envs=6, steps=60)),
+            ("terrain_golden", lambda: terrain.check_hand_worked(libpath)),
+            ("terrain_plain", lambda: terrain.check_reduces_to_plain(libpath, n_envs=12, steps=60)),
+            ("terrain_generation", lambda: terrain.check_generation(rocrand_philox, libpath)),
+            ("terrain_chances", lambda: terrain.check_chances(libpath)),
+            ("terrain_invariants",
+             lambda: terrain.check_trajectory_invariants(libpath, n_envs=40, steps=100))]
     for name, fn in pins:
         try:
             fn()

@@ -41,6 +41,9 @@ DESCR = {
                   "discovery-map output (32 words per env)",
     "multi10": "4096 envs, 32x32 grid, 15% iid walls, 5 seekers + 5 hiders, 9x9 window, "
                "4 channels, collisions in agent order",
+    "terrain4k": "4096 envs, 32x32 grid, 10% walls, 15% water, 10% mud, 5 seekers + 5 hiders "
+                 "of cycling classes (walker, swimmer, flyer), move chances, stuck 25% and "
+                 "rescue, 9x9 window, 4 channels",
     "uneven8k": "8192 envs: sides {16,32,64} (50/30/20%), 1..10 agents, 5..25% walls, "
                 "radius 2..4, 4 channels",
 }
@@ -52,6 +55,7 @@ def words(r: int) -> int:
 
 
 EXPLORE = 16
+TERRAIN = 32
 
 
 def map_bytes(s) -> int:
@@ -71,13 +75,17 @@ def state_bytes_per_launch(specs) -> int:
     """Bytes a launch must read and write once: per-env spec/offset/key words
     and counters (read 56 B, plus the map offset for envs with line of sight
     or exploration; write 16 B), agent positions (2 B each way), the padded
-    wall bitboard (read) and the discovery map of an exploring env (read and
-    write)."""
+    wall bitboard (read; two tile planes with terrain, plus its 24 B of
+    classes and chances and the stuck word both ways) and the discovery map
+    of an exploring env (read and write)."""
     tot = 0
     for s in specs:
         P = (s["W"] + 8 + 31) // 32
         board = 4 * ((s["H"] + 8) * P + 1)
         feat = 4 if s["flags"] & (8 | EXPLORE) else 0
+        if s["flags"] & TERRAIN:
+            # second tile plane, terrain words (24 B), stuck word both ways
+            feat, board = feat + 24 + 8, 2 * board
         tot += 56 + feat + 16 + 4 * s["n"] + board + 2 * map_bytes(s)
     return tot
 

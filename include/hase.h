@@ -67,6 +67,19 @@ extern "C" {
  * the map; its reward is (128 * detections + new cells) / 128. The map after
  * each step is the optional output of hase_step_maps. */
 #define HASE_EXPLORE 16u
+/* terrain (Sec. 3.2 traversal kinetics, collision models and agent-tile move
+ * speed; the tile flags W/A/F/B and the AgentState stuck / walk / fly / swim
+ * bits of Fig. "Bit Packing Environment Structure"): cells are ground
+ * (walkable, flyable), wall (blocking), water (aquatic, flyable) or mud
+ * (walkable, flyable, sticky); agents are walkers (ground, mud), swimmers
+ * (water) or flyers (all but walls). A move onto a tile the agent's class may
+ * not enter is blocked; an allowed move succeeds with the (class, tile) move
+ * chance; a walker entering mud gets stuck with the stuck chance; a stuck
+ * agent does not move until, after the moves of a step, a teammate that is
+ * not stuck stands within Chebyshev distance 1. Observation channel 0 holds
+ * the tiles the agent's class may not enter. Not combinable with
+ * HASE_OCCLUDE (HASE_EINVAL). */
+#define HASE_TERRAIN 32u
 
 /* step modes */
 #define HASE_STEP_PERSISTENT 0u  /* all n_steps in one launch per tile variant (graph-replayed) */
@@ -83,14 +96,31 @@ extern "C" {
  *   n_channels     3 (blocked, teammate, opponent) or 4 (+ outside-the-map)
  *   wall_pct       0..99: each cell is an iid blocking tile with this
  *                  probability (integer threshold, see hase_reset)
- *   flags          HASE_COLLIDE | HASE_CAPTURE_ENDS | HASE_DESYNC
+ *   flags          HASE_COLLIDE | HASE_CAPTURE_ENDS | HASE_DESYNC |
+ *                  HASE_OCCLUDE | HASE_EXPLORE | HASE_TERRAIN
  *   episode_len    L in 1..65535: truncation when t reaches L
+ * Terrain fields (read only with HASE_TERRAIN; 0 otherwise):
+ *   water_pct, mud_pct  percent of water and mud cells, wall_pct + water_pct
+ *                  + mud_pct <= 99 (the same draw per cell as the walls: wall
+ *                  below floor(wall_pct 2^32 / 100), else water below the
+ *                  threshold of wall_pct + water_pct, else mud below that of
+ *                  the three, else ground)
+ *   stuck_pct      0..100, chance that a walker entering mud gets stuck
+ *   speed_pct      0..100, chance that a move onto a tile succeeds, index
+ *                  class * 3 + tile (classes walker, swimmer, flyer; tiles
+ *                  ground, water, mud)
+ *   agent_classes  2 bits per agent (bits 2i, 2i+1 for agent i): 0 walker,
+ *                  1 swimmer, 2 flyer; 0 for i >= n_agents
+ * Chances: a 32-bit draw x meets p percent iff x * 100 < p * 2^32.
  */
 typedef struct hase_env_spec {
     uint16_t height, width;
     uint8_t n_agents, n_seekers, view_radius, n_channels;
     uint8_t wall_pct, flags;
     uint16_t episode_len;
+    uint8_t water_pct, mud_pct, stuck_pct;
+    uint8_t speed_pct[9];
+    uint64_t agent_classes;
 } hase_env_spec;
 
 /*
@@ -137,13 +167,17 @@ typedef struct hase_layout {
 /*
  * Host-side state of a batch (checkpoint / test loading). All arrays are
  * host memory owned by the caller, sized from hase_layout:
- *   walls    [cells_total] uint8, env e's H*W cells row-major, 1 = blocking
+ *   walls    [cells_total] uint8, env e's H*W cells row-major: 1 = blocking,
+ *            0 = open; HASE_TERRAIN envs: the tile type, 0 ground, 1 wall,
+ *            2 water, 3 mud (set_state rejects other values: HASE_ESTATE)
  *   pos_x/y  [agents_total] uint8 (x < W, y < H)
  *   found    [n_envs] hiders found this episode (bit i = agent i)
  *   t        [n_envs] steps elapsed in the episode
  *   episode  [n_envs] episode index since the reset
  *   steps    [n_envs] step calls since the reset (the generator's step key)
  *   seed     [n_envs] generator seed
+ *   stuck    [n_envs] bit i: agent i is stuck (HASE_TERRAIN envs); may be
+ *            NULL: get_state skips it and set_state clears it
  *   discovered [map_words_per_step] discovery maps of the HASE_EXPLORE envs
  *            (the map layout above); may be NULL: get_state then skips the
  *            maps and set_state clears every map; set_state rejects a map
@@ -156,6 +190,7 @@ typedef struct hase_host_state {
     uint32_t *found, *t, *episode, *steps;
     uint64_t *seed;
     uint32_t *discovered;
+    uint32_t *stuck;
 } hase_host_state;
 
 typedef struct hase_batch hase_batch;

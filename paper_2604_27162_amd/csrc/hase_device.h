@@ -67,7 +67,7 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 }
 
 // Counter layout: (env id, stream << 24 | sub, a, b).
-enum : uint32_t { ST_ACTION = 0u, ST_SPAWN = 1u, ST_WALL = 2u, ST_DESYNC = 3u };
+enum : uint32_t { ST_ACTION = 0u, ST_SPAWN = 1u, ST_WALL = 2u, ST_DESYNC = 3u, ST_MOVE = 4u };
 
 // floor(x * m / 2^32)
 __device__ __forceinline__ uint32_t range_map(uint32_t x, uint32_t m) { return __umulhi(x, m); }
@@ -97,13 +97,15 @@ __device__ __forceinline__ uint32_t board_bit(const uint32_t *slot, int pc)
 }
 
 // Agent spawn for episode ep: agents in index order, up to 64 uniform draws
-// each, first cell that is open and not held by an earlier agent; if every
-// draw fails, the first acceptable cell scanning row-major from the cell after
-// the last draw, wrapping around. Positions (packed padded cells) are written
-// to out[0..n) in LDS; the loops are not unrolled (spawning is rare), and all
-// lanes of an env may run it together since they write identical values.
-__device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, const uint32_t *slot,
-                                             uint32_t env, uint32_t k0, uint32_t k1, uint32_t ep)
+// each, first cell that agent i may stand on (ok(i, cell)) and no earlier
+// agent holds; if every draw fails, the first acceptable cell scanning
+// row-major from the cell after the last draw, wrapping around. Positions
+// (packed padded cells) are written to out[0..n) in LDS; the loops are not
+// unrolled (spawning is rare), and all lanes of an env may run it together
+// since they write identical values.
+template <typename OK>
+__device__ __forceinline__ void spawn_agents_if(int *out, int n, int H, int W, uint32_t env,
+                                                uint32_t k0, uint32_t k1, uint32_t ep, OK ok_fn)
 {
     const uint32_t cells = (uint32_t)(H * W);
     for (int i = 0; i < n; ++i) {
@@ -114,7 +116,7 @@ __device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, cons
             c = range_map(x.x, cells);
             const uint32_t y = c / (uint32_t)W, xx = c - y * (uint32_t)W;
             const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
-            bool ok = board_bit(slot, pc) == 0u;
+            bool ok = ok_fn(i, pc);
             for (int k = 0; k < i && ok; ++k) ok = out[k] != pc;
             if (ok) {
                 out[i] = pc;
@@ -126,7 +128,7 @@ __device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, cons
             if (cc >= cells) cc -= cells;
             const uint32_t y = cc / (uint32_t)W, xx = cc - y * (uint32_t)W;
             const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
-            bool ok = board_bit(slot, pc) == 0u;
+            bool ok = ok_fn(i, pc);
             for (int k = 0; k < i && ok; ++k) ok = out[k] != pc;
             if (ok) {
                 out[i] = pc;
@@ -134,6 +136,37 @@ __device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, cons
             }
         }
     }
+}
+
+// Plain spawn: any open cell of the board.
+__device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, const uint32_t *slot,
+                                             uint32_t env, uint32_t k0, uint32_t k1, uint32_t ep)
+{
+    spawn_agents_if(out, n, H, W, env, k0, k1, ep,
+                    [&](int, int pc) { return board_bit(slot, pc) == 0u; });
+}
+
+// ------------------------------------------------------------ terrain
+
+// Tile types are two board planes (plane 0 = wall or mud, plane 1 = water or
+// mud; outside reads as wall: 1, 0). Agent classes: 0 walker (ground, mud),
+// 1 swimmer (water), 2 flyer (anything but walls). Cells an agent of class
+// cls may not enter, from plane bits b0, b1 (any width of bits at once).
+__device__ __forceinline__ uint32_t class_blocked(uint32_t cls, uint32_t b0, uint32_t b1)
+{
+    return cls == 0u ? (b0 ^ b1) : (cls == 1u ? (b0 | ~b1) : (b0 & ~b1));
+}
+
+// Class of agent i from the two class words (2 bits per agent).
+__device__ __forceinline__ uint32_t agent_class(uint32_t lo, uint32_t hi, int i)
+{
+    return ((i < 16 ? lo : hi) >> (2 * (i & 15))) & 3u;
+}
+
+// A uniform word x meets a chance of pct percent: x / 2^32 < pct / 100.
+__device__ __forceinline__ bool chance(uint32_t x, uint32_t pct)
+{
+    return (uint64_t)x * 100u < ((uint64_t)pct << 32);
 }
 
 // ------------------------------------------------------------ step kernel
@@ -162,11 +195,13 @@ __device__ __forceinline__ void wave_lds_fence()
 }
 
 // Window rows of one agent into W-word bitmasks (bit k = row * D + column),
-// fully unrolled for radius R: wall|outside from the padded board and, for
-// 4-channel envs, outside-the-map only.
-template <int R, int W>
+// fully unrolled for radius R: wall|outside from the padded board (TER: the
+// cells the agent's class cls may not enter, from the two tile planes, plane
+// 1 pw words after plane 0) and, for 4-channel envs, outside-the-map only.
+template <int R, int W, bool TER = false>
 __device__ __forceinline__ void window_rows(const uint32_t *slot, int H, int Wd, int ax, int ay,
-                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W])
+                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
+                                            int pw = 0, uint32_t cls = 0u)
 {
     constexpr int D = 2 * R + 1;
     constexpr uint32_t DM = (1u << D) - 1u;
@@ -177,7 +212,10 @@ __device__ __forceinline__ void window_rows(const uint32_t *slot, int H, int Wd,
 #pragma unroll
     for (int rho = 0; rho < D; ++rho) {
         const uint32_t *rp = base + rho * LDS_ROW;
-        const uint32_t bits = __builtin_amdgcn_alignbit(rp[1], rp[0], sh) & DM;
+        uint32_t bits = __builtin_amdgcn_alignbit(rp[1], rp[0], sh);
+        if constexpr (TER)
+            bits = class_blocked(cls, bits, __builtin_amdgcn_alignbit(rp[pw + 1], rp[pw], sh));
+        bits &= DM;
         const int off = rho * D, wi = off >> 5, b = off & 31;
         wall[wi] |= bits << b;
         if (b + D > 32) wall[wi + 1] |= bits >> (32 - b);
@@ -278,18 +316,19 @@ constexpr uint64_t MOVE_TABLE = 0x101ull | (0x001ull << 12) | (0x201ull << 24) |
 // only agent on the centre cell is the agent itself. exact == true tests
 // every other agent by index. Returns the number of other-role agents in the
 // window (Chebyshev distance <= R).
-template <int R, int W, int NMAX, bool EXACT>
+template <int R, int W, int NMAX, bool EXACT, bool TER = false>
 __device__ __forceinline__ int agent_masks_raw(const uint32_t *slot, int H, int Wd,
                                            const int (&pp)[NMAX], int a, int pa, int n, int S,
                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
-                                           uint32_t (&team)[W], uint32_t (&opp)[W])
+                                           uint32_t (&team)[W], uint32_t (&opp)[W], int pw = 0,
+                                           uint32_t cls = 0u)
 {
     constexpr int D = 2 * R + 1;
     constexpr int CENTER = R * D + R;
 #pragma unroll
     for (int i = 0; i < W; ++i) wall[i] = outm[i] = team[i] = opp[i] = 0u;
     const int ax = pa & 0xff, ay = pa >> 8;
-    window_rows<R, W>(slot, H, Wd, ax, ay, want_out, wall, outm);
+    window_rows<R, W, TER>(slot, H, Wd, ax, ay, want_out, wall, outm, pw, cls);
     const bool sa = a < S;
     if constexpr (!EXACT && NMAX <= 4) {
         // Distinct cells: the agent itself is the centre (in no channel) and
@@ -557,18 +596,19 @@ __device__ __forceinline__ int occlude(const int (&pp)[NMAX], int a, int pa, int
 // the visible cells and the opponent count to visible opponents; with
 // exploration (xpl) seen gets the window cells that are visible and inside
 // the map (bits past the window's D*D cells are undefined).
-template <int R, int W, int NMAX, bool EXACT, bool FEAT>
+template <int R, int W, int NMAX, bool EXACT, bool FEAT, bool TER>
 __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
                                            const int (&pp)[NMAX], int a, int pa, int n, int S,
                                            bool want_out, bool occl, bool xpl, uint32_t (&wall)[W],
                                            uint32_t (&outm)[W], uint32_t (&team)[W],
-                                           uint32_t (&opp)[W], uint32_t (&seen)[W])
+                                           uint32_t (&opp)[W], uint32_t (&seen)[W], int pw,
+                                           uint32_t cls)
 {
     // exploration needs the outside-the-map cells whatever the channel count
     // (outm is stored only for 4-channel envs)
-    int cnt = agent_masks_raw<R, W, NMAX, EXACT>(slot, H, Wd, pp, a, pa, n, S,
-                                                 FEAT ? (want_out || xpl) : want_out, wall, outm,
-                                                 team, opp);
+    int cnt = agent_masks_raw<R, W, NMAX, EXACT, TER>(slot, H, Wd, pp, a, pa, n, S,
+                                                      FEAT ? (want_out || xpl) : want_out, wall,
+                                                      outm, team, opp, pw, cls);
     if constexpr (FEAT) {
         uint32_t vis[W];
 #pragma unroll
@@ -580,20 +620,24 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
     return cnt;
 }
 
-template <int R, int W, int NMAX, int TPL, bool EXACT, bool FEAT>
+template <int R, int W, int NMAX, int TPL, bool EXACT, bool FEAT, bool TER = false>
 __device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
                                           const int (&pp)[NMAX], int l, int lanes,
                                           const int (&mine)[TPL], int n, int S, bool want_out,
                                           bool occl, bool xpl, uint32_t (&wall)[TPL][W],
                                           uint32_t (&outm)[TPL][W], uint32_t (&team)[TPL][W],
                                           uint32_t (&opp)[TPL][W], uint32_t (&seen)[TPL][W],
-                                          int (&cnt)[TPL])
+                                          int (&cnt)[TPL], int pw = 0, uint32_t clo = 0u,
+                                          uint32_t chi = 0u)
 {
 #pragma unroll
-    for (int m = 0; m < TPL; ++m)
-        cnt[m] = agent_masks<R, W, NMAX, EXACT, FEAT>(slot, H, Wd, pp, l + m * lanes, mine[m], n,
-                                                      S, want_out, occl, xpl, wall[m], outm[m],
-                                                      team[m], opp[m], seen[m]);
+    for (int m = 0; m < TPL; ++m) {
+        const int a = l + m * lanes;
+        const uint32_t cls = TER ? agent_class(clo, chi, a) : 0u;
+        cnt[m] = agent_masks<R, W, NMAX, EXACT, FEAT, TER>(slot, H, Wd, pp, a, mine[m], n, S,
+                                                           want_out, occl, xpl, wall[m], outm[m],
+                                                           team[m], opp[m], seen[m], pw, cls);
+    }
 }
 
 // ------------------------------------------------------------ exploration
@@ -761,7 +805,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // from the previous step's windows instead of board reads, and detection
     // (rewards, found bits) is a pairwise Chebyshev test in every lane of the
     // env, independent of the observation masks
-    constexpr bool NBR = NMAX <= 4;
+    constexpr bool NBR = NMAX <= 4 && (KIND & KIND_TERRAIN) == 0;
     constexpr bool PAIRS = NMAX <= 4;
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
 
@@ -783,12 +827,28 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     const bool want_out = C == 4;
     constexpr bool FEAT_OK = KIND != KIND_PLAIN;
     constexpr bool XPL = (KIND & KIND_EXPLORE) != 0;  // every env of the tile explores
+    constexpr bool TER = (KIND & KIND_TERRAIN) != 0;  // every env of the tile has terrain
 
     const uint32_t obs_off = gp(J.tab.obs_off)[e], agent_off = gp(J.tab.agent_off)[e];
     const uint32_t env = gp(J.tab.env_id)[e];
     const uint64_t seed = gp(J.seed)[e];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     uint32_t found = gp(J.found)[e], t = gp(J.t)[e], ep = gp(J.ep)[e], steps = gp(J.steps)[e];
+    // terrain: the second tile plane pw words after the first, the stuck
+    // chance (bits 16..23 of word 0), the move chances (bytes of words 1..3,
+    // class * 3 + tile), the agent classes (words 4, 5) and the stuck agents
+    const int pw = TER ? (H + 2 * PAD) * LDS_ROW + 1 : 0;
+    uint32_t tch = 0u, sp_a = 0u, sp_b = 0u, sp_c = 0u, clo = 0u, chi = 0u, stuck = 0u;
+    if constexpr (TER) {
+        const GAS uint32_t *tr = gp(J.tab.terr) + 8u * e;
+        tch = tr[0];
+        sp_a = tr[1];
+        sp_b = tr[2];
+        sp_c = tr[3];
+        clo = tr[4];
+        chi = tr[5];
+        stuck = gp(J.stuck)[e];
+    }
 
     // this env's LDS slot: the padded bitboard, then MAX_AGENTS words where a
     // respawn writes the new positions, then (feature launches with an
@@ -801,12 +861,15 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         if (K != 0u) map_load<LANES>(mslot, gp(J.disc) + map_off, H, Wd, l);
     }
     {
-        // rows of P words in HBM -> rows of LDS_ROW words (unused words 0)
+        // rows of P words in HBM -> rows of LDS_ROW words (unused words 0);
+        // terrain envs have two planes, each one HBM board long
         const GAS uint32_t *src = gp(J.bb) + gp(J.tab.bb_off)[e];
         const int bw = (H + 2 * PAD) * LDS_ROW + 1;
-        for (int i = l; i < bw; i += LANES) {
-            const int y = i / LDS_ROW, x = i - y * LDS_ROW;
-            slot[i] = x < P ? src[y * P + x] : 0u;
+        const int hw = (H + 2 * PAD) * P + 1;
+        for (int i = l; i < (TER ? 2 * bw : bw); i += LANES) {
+            const int pl = i >= bw ? 1 : 0, j = i - pl * bw;
+            const int y = j / LDS_ROW, x = j - y * LDS_ROW;
+            slot[i] = x < P ? src[pl * hw + y * P + x] : 0u;
         }
     }
     const uint32_t last_word = slot_words - 1u;
@@ -937,8 +1000,9 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         };
 
         if (obs_only) {
-            all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                               LOS, false, wall, outm, team, opp, seen, cnt);
+            all_masks<R, W, NMAX, TPL, EX, OC, TER>(slot, H, Wd, pp, l, LANES, mine, n, S,
+                                                    want_out, LOS, false, wall, outm, team, opp,
+                                                    seen, cnt, pw, clo, chi);
 #pragma unroll
             for (int m = 0; m < TPL; ++m)
                 if (mine_live[m]) store_obs(m);
@@ -968,7 +1032,57 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             acts &= amask;
 
             // ---- 2 moves, agent-index order (redundant in every lane of the env)
-            if constexpr (NBR) {
+            if constexpr (TER) {
+                // Terrain: a stuck agent stays; the target must be a tile the
+                // agent's class may enter and (collisions on) free; then the
+                // move chance and, for a walker entering mud, the stuck chance
+                // decide, from words 2(i&1) and 2(i&1)+1 of the MOVE block of
+                // agent pair i>>1 at this step.
+                U4 blk = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;  // 0 for absent agents
+                    const int tg = pp[i] + (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
+                    uint32_t widx = (uint32_t)(tg >> 8) * (uint32_t)LDS_ROW + (((uint32_t)tg >> 5) & 7u);
+                    widx = widx < (uint32_t)pw - 1u ? widx : (uint32_t)pw - 1u;  // parked agents
+                    const uint32_t sh = (uint32_t)tg & 31u;
+                    const uint32_t b0 = (slot[widx] >> sh) & 1u, b1 = (slot[pw + widx] >> sh) & 1u;
+                    const uint32_t cls = agent_class(clo, chi, i);
+                    uint32_t occ = 0u;
+#pragma unroll
+                    for (int jj = 0; jj < NMAX; ++jj)
+                        if (jj != i) occ |= ((uint32_t)(tg ^ pp[jj]) - 1u) >> 31;
+                    const bool cand = a != 0u && ((stuck >> i) & 1u) == 0u &&
+                                      (class_blocked(cls, b0, b1) & 1u) == 0u && (occ & cmask) == 0u;
+                    if ((i & 1) == 0 && i < n)
+                        blk = philox(env, (ST_MOVE << 24) | (uint32_t)(i >> 1), steps, 0u, k0, k1);
+                    const uint32_t u = (i & 1) ? blk.z : blk.x, v = (i & 1) ? blk.w : blk.y;
+                    const uint32_t type = b0 | (b1 << 1);  // ground, wall, water, mud
+                    const uint32_t tile = type == 0u ? 0u : (type == 2u ? 1u : 2u);
+                    const uint32_t k = cls * 3u + tile;
+                    const uint32_t pct = ((k < 4u ? sp_a : (k < 8u ? sp_b : sp_c)) >> (8u * (k & 3u))) & 0xffu;
+                    const bool go = cand && chance(u, pct);
+                    if (go && cls == 0u && type == 3u && chance(v, (tch >> 16) & 0xffu)) stuck |= 1u << i;
+                    pp[i] = go ? tg : pp[i];
+                }
+                // rescue: freed by a teammate that is not stuck within
+                // Chebyshev distance 1 after the moves ((dy + 1) << 8 | (dx + 1)
+                // has both bytes below 3 exactly then)
+                const uint32_t before = stuck;
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    bool freed = false;
+#pragma unroll
+                    for (int jj = 0; jj < NMAX; ++jj) {
+                        if (jj == i) continue;
+                        const uint32_t du = (uint32_t)(pp[i] - pp[jj]) + 257u;
+                        const uint32_t lo = du & 0xffu, hi = du >> 8;
+                        const bool near = (lo > hi ? lo : hi) < 3u;
+                        freed |= jj < n && (jj < S) == (i < S) && near && ((before >> jj) & 1u) == 0u;
+                    }
+                    if (freed) stuck &= ~(1u << i);
+                }
+            } else if constexpr (NBR) {
                 // Integer decisions only: lane-mask logic would cost a round
                 // trip through the scalar unit on the step's critical path. A
                 // move is blocked by its field bit or, with collisions on, by
@@ -1018,8 +1132,9 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
             // ---- 3 detection at the post-move positions, and the channels
-            all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S, want_out,
-                                               LOS, XP, wall, outm, team, opp, seen, cnt);
+            all_masks<R, W, NMAX, TPL, EX, OC, TER>(slot, H, Wd, pp, l, LANES, mine, n, S,
+                                                    want_out, LOS, XP, wall, outm, team, opp,
+                                                    seen, cnt, pw, clo, chi);
             // The role channels feed only the (predicated) stores, so the
             // compiler would compute them inside the store region; using them
             // here keeps them in the step's main block, where they fill the
@@ -1116,14 +1231,26 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 // the new episode starts with an empty discovery map
                 if constexpr (XP)
                     for (uint32_t i = (uint32_t)l; i < map_words; i += LANES) mslot[i] = 0u;
-                spawn_agents(spawned, n, H, Wd, slot, env, k0, k1, ep);
+                if constexpr (TER) {
+                    // and with nobody stuck; each agent on a tile of its class
+                    stuck = 0u;
+                    spawn_agents_if(spawned, n, H, Wd, env, k0, k1, ep, [&](int i, int pc) {
+                        const int yy = pc >> 8, xx = pc & 0xff;
+                        const int wi = yy * LDS_ROW + (xx >> 5);
+                        const uint32_t b0 = (slot[wi] >> (xx & 31)) & 1u;
+                        const uint32_t b1 = (slot[pw + wi] >> (xx & 31)) & 1u;
+                        return (class_blocked(agent_class(clo, chi, i), b0, b1) & 1u) == 0u;
+                    });
+                } else {
+                    spawn_agents(spawned, n, H, Wd, slot, env, k0, k1, ep);
+                }
                 wave_lds_fence();
 #pragma unroll
                 for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
                 own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-                all_masks<R, W, NMAX, TPL, EX, OC>(slot, H, Wd, pp, l, LANES, mine, n, S,
-                                                   want_out, LOS, false, wall, outm, team, opp,
-                                                   seen, cnt);
+                all_masks<R, W, NMAX, TPL, EX, OC, TER>(slot, H, Wd, pp, l, LANES, mine, n, S,
+                                                        want_out, LOS, false, wall, outm, team,
+                                                        opp, seen, cnt, pw, clo, chi);
 #pragma unroll
                 for (int m = 0; m < TPL; ++m)
                     if (mine_live[m]) store_obs(m);
@@ -1265,6 +1392,9 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         if constexpr (XPL) {
             wave_lds_fence();
             map_store<LANES>(gp(J.disc) + map_off, mslot, H, Wd, l);
+        }
+        if constexpr (TER) {
+            if (l == 0) gp(J.stuck)[e] = stuck;
         }
     }
 }

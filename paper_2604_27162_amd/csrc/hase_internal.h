@@ -7,7 +7,8 @@
 
 namespace hase {
 
-// Every grid is stored on the device as a padded row bitboard: PAD cells of
+// Every grid is stored on the device as a padded row bitboard (terrain envs:
+// two of them, the tile-type planes, one after the other): PAD cells of
 // "outside" on each side (PAD >= the largest view radius, so windows and move
 // targets never leave the board), bit x' of padded row y' in word
 // y' * P + (x' >> 5), P = ceil((W + 2 PAD) / 32). Cells outside the map read
@@ -43,6 +44,9 @@ struct EnvTables {
     const uint32_t *spec0, *spec1, *spec2;
     const uint32_t *obs_off, *agent_off, *bb_off, *grid_off, *env_id;
     const uint32_t *map_off;  // first discovery-map word (exploring envs)
+    // terrain envs, 8 words per env: stuck chance << 16 (word 0), move chances
+    // (bytes of words 1..3, class * 3 + tile), agent classes (words 4, 5)
+    const uint32_t *terr;
 };
 
 // Discovery map of an exploring env in HBM (state and per-step output): H
@@ -70,6 +74,7 @@ struct JobDesc {
     uint32_t k_limit;     // steps this job may take in one launch
     uint32_t out_step0;   // output step index of the job's first step in this launch
     uint32_t *disc;       // discovery maps (state), at tab.map_off[e]
+    uint32_t *stuck;      // stuck agents per env (terrain)
     uint32_t *map;        // per-step map output, may be null
     uint64_t map_stride;  // map words per output step
 };
@@ -89,6 +94,7 @@ struct InitArgs {
     uint8_t *walls;
     uint32_t *bb;
     uint32_t *disc;       // discovery maps, cleared at reset
+    uint32_t *stuck;      // stuck agents, cleared at reset
     uint32_t *err;        // min over envs with too few free cells (reset only)
     uint64_t seed_value;
     uint32_t n_envs;
@@ -98,13 +104,15 @@ struct InitArgs {
 // Env kinds: each kind has its own step loop and its own kernels (so the
 // register allocation of one never burdens another), and a tile holds envs
 // of one kind only.
-constexpr int KIND_PLAIN = 0;    // no line of sight, no exploration
+constexpr int KIND_PLAIN = 0;    // no line of sight, no exploration, no terrain
 constexpr int KIND_EXPLORE = 1;  // bit 0: exploration
 constexpr int KIND_LOS = 2;      // bit 1: line of sight
-constexpr int N_KINDS = 4;       // plain, exploration, line of sight, both
+constexpr int KIND_TERRAIN = 4;  // bit 2: terrain (never with line of sight)
+constexpr int N_KINDS = 6;       // kinds 0..5
 inline int env_kind(uint32_t flags)
 {
-    return ((flags & 8u) ? KIND_LOS : 0) | ((flags & 16u) ? KIND_EXPLORE : 0);
+    return ((flags & 8u) ? KIND_LOS : 0) | ((flags & 16u) ? KIND_EXPLORE : 0) |
+           ((flags & 32u) ? KIND_TERRAIN : 0);
 }
 
 // Launch the step kernel for tile range [tile0, tile0 + n_tiles) of variant
@@ -116,8 +124,9 @@ hipError_t launch_step(int lanes, int nmax, int r, const Tile *tiles, uint32_t n
 
 // One launch over tiles of several (bucket, radius) variants that share
 // `lanes`, all envs of kind `kind`; slot_words is the largest board among
-// them, map_words the LDS words of a discovery map per env (slot_words when
-// an env of the range explores, else 0).
+// them (both tile planes for terrain), map_words the LDS words of a
+// discovery map per env (the largest one-plane board among the exploring
+// envs, else 0).
 hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles,
                         const JobDesc *jobs, const JobDesc &job0, uint32_t K, uint32_t step_base,
                         uint32_t slot_words, uint32_t map_words, hipStream_t stream);
@@ -125,8 +134,9 @@ hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles
 hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 
 // Per-lanes entry points, one translation unit each: single-variant and
-// mixed plain kernels (hase_step_l<L>.hip, hase_mixed_l<L>.hip), and the
-// feature kinds (hase_feat_l<L>.hip).
+// mixed plain kernels (hase_step_l<L>.hip, hase_mixed_l<L>.hip), the line of
+// sight and exploration kinds (hase_feat_l<L>.hip) and the terrain kinds
+// (hase_terr_l<L>.hip).
 #define HASE_DECLARE_LANES(L)                                                                     \
     hipError_t launch_step_lanes##L(int nmax, int r, const Tile *tiles, uint32_t n_tiles,        \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
@@ -136,6 +146,10 @@ hipError_t launch_init(const InitArgs &a, hipStream_t stream);
                                      uint32_t slot_words, uint32_t map_words,                     \
                                      hipStream_t stream);                                         \
     hipError_t launch_feat_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,               \
+                                    const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
+                                    uint32_t step_base, uint32_t slot_words, uint32_t map_words,  \
+                                    hipStream_t stream);                                          \
+    hipError_t launch_terr_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,               \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
                                     uint32_t step_base, uint32_t slot_words, uint32_t map_words,  \
                                     hipStream_t stream);

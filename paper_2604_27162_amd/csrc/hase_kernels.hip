@@ -8,13 +8,13 @@ namespace hase {
 
 // ------------------------------------------------------------ init kernel
 
-// One 64-lane block per env: walls from the generator (reset) or loaded
-// (rebuild), padded bitboard, free-cell check, spawn of episode 0, desync,
-// empty discovery map (exploring envs).
+// One 64-lane block per env: walls (terrain: tile types) from the generator
+// (reset) or loaded (rebuild), padded board planes, free-cell check, spawn of
+// episode 0, desync, empty discovery map (exploring envs), nobody stuck.
 __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
 {
     __shared__ uint8_t cellw[MAX_SIDE * MAX_SIDE];
-    __shared__ uint32_t board[(MAX_SIDE + 2 * PAD) * LDS_ROW + 1];
+    __shared__ uint32_t board[2][(MAX_SIDE + 2 * PAD) * LDS_ROW + 1];
     __shared__ int spawned[MAX_AGENTS];
     const uint32_t e = blockIdx.x;
     const int lane = (int)threadIdx.x;
@@ -28,10 +28,19 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
     const uint32_t env = A.tab.env_id[e];
     uint8_t *walls = A.walls + A.tab.grid_off[e];
     const uint32_t k0 = (uint32_t)A.seed_value, k1 = (uint32_t)(A.seed_value >> 32);
+    const bool terrain = (flags & 32u) != 0u;
+    // terrain word 0: water % | mud % << 8 | stuck % << 16; words 4, 5: classes
+    const uint32_t tw0 = terrain ? A.tab.terr[8u * e] : 0u;
+    const uint32_t clo = terrain ? A.tab.terr[8u * e + 4u] : 0u;
+    const uint32_t chi = terrain ? A.tab.terr[8u * e + 5u] : 0u;
 
     if (!A.rebuild_only) {
-        // a cell is blocking iff its word is below floor(pct * 2^32 / 100)
+        // a cell is blocking iff its word is below floor(pct * 2^32 / 100);
+        // with terrain, water / mud below the cumulative thresholds
         const uint32_t T = (uint32_t)(((uint64_t)wall_pct << 32) / 100u);
+        const uint32_t Tw = (uint32_t)(((uint64_t)(wall_pct + (tw0 & 0xffu)) << 32) / 100u);
+        const uint32_t Tm =
+            (uint32_t)(((uint64_t)(wall_pct + (tw0 & 0xffu) + ((tw0 >> 8) & 0xffu)) << 32) / 100u);
         for (int g = lane; 4 * g < cells; g += 64) {
             const U4 x = philox(env, (ST_WALL << 24) | (uint32_t)g, 0u, 0u, k0, k1);
             const uint32_t v[4] = {x.x, x.y, x.z, x.w};
@@ -39,40 +48,46 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
             for (int m = 0; m < 4; ++m) {
                 const int c = 4 * g + m;
                 if (c < cells) {
-                    const uint8_t b = v[m] < T ? 1 : 0;
+                    uint8_t b = v[m] < T ? 1 : 0;
+                    if (terrain && b == 0) b = v[m] < Tw ? 2 : (v[m] < Tm ? 3 : 0);
                     cellw[c] = b;
                     walls[c] = b;
                 }
             }
         }
     } else {
-        for (int c = lane; c < cells; c += 64) cellw[c] = walls[c] ? 1 : 0;
+        for (int c = lane; c < cells; c += 64)
+            cellw[c] = terrain ? (uint8_t)(walls[c] & 3u) : (uint8_t)(walls[c] ? 1 : 0);
     }
     __syncthreads();
 
-    // HBM board: rows of P words; the LDS copy used by the spawn below has
-    // rows of LDS_ROW words (unused words 0), as in the step kernel
+    // HBM board planes: rows of P words (plane 1 after plane 0, terrain
+    // only); the LDS copies used by the spawn below have rows of LDS_ROW
+    // words (unused words 0), as in the step kernel. Plane 0: wall or mud
+    // (outside: 1), plane 1: water or mud (outside: 0).
     const int rows = H + 2 * PAD;
     const int bw = rows * P + 1;
-    for (int i = lane; i < rows * LDS_ROW + 1; i += 64) board[i] = 0u;
+    for (int i = lane; i < rows * LDS_ROW + 1; i += 64) board[0][i] = board[1][i] = 0u;
     __syncthreads();
-    for (int i = lane; i < bw; i += 64) {
-        uint32_t word = 0xffffffffu;  // slack word
-        const int yy = i / P, j = i - (i / P) * P;
-        if (i < rows * P) {
-            word = 0;
-            for (int b = 0; b < 32; ++b) {
-                const int xx = 32 * j + b;
-                const bool out = yy < PAD || yy >= H + PAD || xx < PAD || xx >= W + PAD;
-                bool v = true;
-                if (!out) v = cellw[(yy - PAD) * W + (xx - PAD)] != 0;
-                word |= (v ? 1u : 0u) << b;
+    for (int pl = 0; pl < (terrain ? 2 : 1); ++pl) {
+        for (int i = lane; i < bw; i += 64) {
+            uint32_t word = 0xffffffffu;  // slack word
+            const int yy = i / P, j = i - (i / P) * P;
+            if (i < rows * P) {
+                word = 0;
+                for (int b = 0; b < 32; ++b) {
+                    const int xx = 32 * j + b;
+                    const bool out = yy < PAD || yy >= H + PAD || xx < PAD || xx >= W + PAD;
+                    bool v = pl == 0;
+                    if (!out) v = ((cellw[(yy - PAD) * W + (xx - PAD)] >> pl) & 1u) != 0;
+                    word |= (v ? 1u : 0u) << b;
+                }
+                board[pl][yy * LDS_ROW + j] = word;
+            } else {
+                board[pl][rows * LDS_ROW] = word;
             }
-            board[yy * LDS_ROW + j] = word;
-        } else {
-            board[rows * LDS_ROW] = word;
+            A.bb[A.tab.bb_off[e] + (uint32_t)(pl * bw + i)] = word;
         }
-        A.bb[A.tab.bb_off[e] + (uint32_t)i] = word;
     }
     __syncthreads();
     if (A.rebuild_only) return;
@@ -81,16 +96,33 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
         for (int i = lane; i < H * ((W + 31) >> 5); i += 64) map[i] = 0u;
     }
 
-    int f = 0;
-    for (int c = lane; c < cells; c += 64) f += cellw[c] ? 0 : 1;
+    // room: free cells (plain), or the cells each class may stand on
+    int f[3] = {0, 0, 0};  // walker, swimmer, flyer
+    for (int c = lane; c < cells; c += 64) {
+        const uint32_t ty = cellw[c];
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) f += __shfl_xor(f, m, 64);
-    if (f < n) {
+        for (int k = 0; k < 3; ++k) f[k] += (class_blocked((uint32_t)k, ty & 1u, ty >> 1) & 1u) ? 0 : 1;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) f[k] += __shfl_xor(f[k], m, 64);
+    bool room = true;
+    for (int i = 0; i < n; ++i) {
+        const uint32_t c = agent_class(clo, chi, i);
+        room = room && (c == 0u ? f[0] : (c == 1u ? f[1] : f[2])) >= n;
+    }
+    if (!room) {
         if (lane == 0) atomicMin(A.err, e);
         return;
     }
     if (lane == 0) {
-        spawn_agents(spawned, n, H, W, board, env, k0, k1, 0u);
+        spawn_agents_if(spawned, n, H, W, env, k0, k1, 0u, [&](int i, int pc) {
+            const int yy = pc >> 8, xx = pc & 0xff;
+            const int wi = yy * LDS_ROW + (xx >> 5);
+            const uint32_t b0 = (board[0][wi] >> (xx & 31)) & 1u, b1 = (board[1][wi] >> (xx & 31)) & 1u;
+            return (class_blocked(agent_class(clo, chi, i), b0, b1) & 1u) == 0u;
+        });
         const uint32_t ao = A.tab.agent_off[e];
         for (int j = 0; j < n; ++j) {
             const uint32_t x = (uint32_t)(spawned[j] & 0xff) - PAD, y = (uint32_t)(spawned[j] >> 8) - PAD;
@@ -100,6 +132,7 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
         A.found[e] = 0;
         A.ep[e] = 0;
         A.steps[e] = 0;
+        A.stuck[e] = 0;
         uint32_t t0 = 0;
         if (flags & 4u) t0 = range_map(philox(env, ST_DESYNC << 24, 0u, 0u, k0, k1).x, Lep);
         A.t[e] = t0;
@@ -139,10 +172,14 @@ hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles
     if (n_tiles == 0) return hipSuccess;
 #define HASE_MIXED_CASE(L)                                                                          \
     case L:                                                                                         \
-        return kind == 0 ? launch_mixed_lanes##L(tiles, n_tiles, jobs, job0, K, step_base,          \
-                                                 slot_words, map_words, stream)                     \
-                         : launch_feat_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base,     \
-                                                slot_words, map_words, stream);
+        if (kind == KIND_PLAIN)                                                                     \
+            return launch_mixed_lanes##L(tiles, n_tiles, jobs, job0, K, step_base, slot_words,      \
+                                         map_words, stream);                                        \
+        if (kind & KIND_TERRAIN)                                                                    \
+            return launch_terr_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base, slot_words, \
+                                        map_words, stream);                                         \
+        return launch_feat_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base, slot_words,     \
+                                    map_words, stream);
     switch (lanes) {
     HASE_MIXED_CASE(1)
     HASE_MIXED_CASE(2)

@@ -80,14 +80,28 @@ int check_spec(const hase_env_spec &s, uint32_t idx)
     if (s.n_channels != 3 && s.n_channels != 4)
         return fail(HASE_EINVAL, "spec %u: n_channels must be 3 or 4", idx);
     if (s.wall_pct > 99) return fail(HASE_EINVAL, "spec %u: wall_pct must be <= 99", idx);
-    if (s.flags & ~31u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
+    if (s.flags & ~63u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
     if (s.episode_len < 1) return fail(HASE_EINVAL, "spec %u: episode_len must be >= 1", idx);
+    if (s.flags & HASE_TERRAIN) {
+        if (s.flags & HASE_OCCLUDE)
+            return fail(HASE_EINVAL, "spec %u: terrain with line of sight is not supported", idx);
+        if ((int)s.wall_pct + s.water_pct + s.mud_pct > 99)
+            return fail(HASE_EINVAL, "spec %u: wall_pct + water_pct + mud_pct must be <= 99", idx);
+        if (s.stuck_pct > 100) return fail(HASE_EINVAL, "spec %u: stuck_pct must be <= 100", idx);
+        for (int k = 0; k < 9; ++k)
+            if (s.speed_pct[k] > 100) return fail(HASE_EINVAL, "spec %u: speed_pct must be <= 100", idx);
+        for (int i = 0; i < 32; ++i) {
+            const uint32_t c = (uint32_t)(s.agent_classes >> (2 * i)) & 3u;
+            if (c == 3u || (i >= s.n_agents && c != 0u))
+                return fail(HASE_EINVAL, "spec %u: agent %d has an invalid class", idx, i);
+        }
+    }
     return HASE_OK;
 }
 
 struct Regions {
-    size_t perm, spec0, spec1, spec2, obs_off, agent_off, bb_off, grid_off, env_id, map_off;
-    size_t seed, found, t, ep, steps, pos, walls, bb, disc, tiles, err, total;
+    size_t perm, spec0, spec1, spec2, obs_off, agent_off, bb_off, grid_off, env_id, map_off, terr;
+    size_t seed, found, t, ep, steps, stuck, pos, walls, bb, disc, tiles, err, total;
 };
 
 struct Plan {
@@ -130,7 +144,8 @@ int make_plan(const hase_batch_desc *d, Plan &p)
         p.obs_words += (uint64_t)s.n_agents * s.n_channels * words_per_channel(s.view_radius);
         p.agents += s.n_agents;
         p.cells += (uint64_t)s.height * s.width;
-        p.bb_words += (uint64_t)board_words(s.height, s.width);
+        // terrain envs keep two board planes (tile types)
+        p.bb_words += (uint64_t)board_words(s.height, s.width) * ((s.flags & HASE_TERRAIN) ? 2 : 1);
         if (s.flags & HASE_EXPLORE) p.map_words += (uint64_t)map_words(s.height, s.width);
     }
     if (p.obs_words >= (1ull << 32) || p.cells >= (1ull << 32) || p.bb_words >= (1ull << 32) ||
@@ -155,11 +170,13 @@ int make_plan(const hase_batch_desc *d, Plan &p)
     r.grid_off = take(4ull * N);
     r.env_id = take(4ull * N);
     r.map_off = take(4ull * N);
+    r.terr = take(32ull * N);
     r.seed = take(8ull * N);
     r.found = take(4ull * N);
     r.t = take(4ull * N);
     r.ep = take(4ull * N);
     r.steps = take(4ull * N);
+    r.stuck = take(4ull * N);
     r.pos = take(2ull * p.agents);
     r.walls = take(p.cells);
     r.bb = take(4ull * p.bb_words);
@@ -222,6 +239,7 @@ struct hase_batch {
         t.grid_off = at<uint32_t>(r.grid_off);
         t.env_id = at<uint32_t>(r.env_id);
         t.map_off = at<uint32_t>(r.map_off);
+        t.terr = at<uint32_t>(r.terr);
         return t;
     }
 };
@@ -274,9 +292,15 @@ int build_tiles(hase_batch *b)
                     const uint32_t base = (uint32_t)perm.size();
                     for (uint32_t e : ids) {
                         perm.push_back(e);
-                        if (p.specs[e].flags & HASE_EXPLORE) grp.xpl = true;
-                        grp.slot_words =
-                            std::max(grp.slot_words, (uint32_t)lds_board_words(p.specs[e].height));
+                        if (p.specs[e].flags & HASE_EXPLORE) {
+                            grp.xpl = true;
+                            grp.map_words = std::max(
+                                grp.map_words, (uint32_t)lds_board_words(p.specs[e].height));
+                        }
+                        // terrain: two tile planes
+                        const int planes = (p.specs[e].flags & HASE_TERRAIN) ? 2 : 1;
+                        grp.slot_words = std::max(
+                            grp.slot_words, (uint32_t)(planes * lds_board_words(p.specs[e].height)));
                     }
                     for (uint32_t i = 0; i < ids.size(); i += E) {
                         Tile t;
@@ -293,7 +317,6 @@ int build_tiles(hase_batch *b)
             }
             if (n_var == 0) continue;
             grp.mixed = n_var > 1 || kind != KIND_PLAIN;
-            grp.map_words = grp.xpl ? grp.slot_words : 0u;
             grp.n_tiles = (uint32_t)tiles.size() - grp.tile0;
             const size_t lds_bytes =
                 (size_t)(64u / L) * (grp.slot_words + MAX_AGENTS + grp.map_words) * 4;
@@ -338,6 +361,7 @@ JobDesc make_job(const hase_batch *b, const int8_t *act, uint32_t *obs, float *r
     j.k_limit = 0xffffffffu;
     j.out_step0 = 0;
     j.disc = b->at<uint32_t>(r.disc);
+    j.stuck = b->at<uint32_t>(r.stuck);
     j.map = map;
     j.map_stride = b->plan.map_words;
     return j;
@@ -373,11 +397,14 @@ int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, h
     return HASE_OK;
 }
 
-int ensure_streams(hase_batch *b)
+// The fork event and the first `count` side streams (created on first use;
+// side stream 0 is also the graph capture stream).
+int ensure_streams(hase_batch *b, size_t count)
 {
-    if (b->fork_ev) return HASE_OK;
-    HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
-    for (int i = 0; i < MAX_LAUNCHES; ++i) {
+    if (count > (size_t)MAX_LAUNCHES) return fail(HASE_EINVAL, "too many launches (%zu)", count);
+    if (!b->fork_ev) HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+    for (size_t i = 0; i < std::max<size_t>(count, 1); ++i) {
+        if (b->side[i]) continue;
         HIP_TRY(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming));
     }
@@ -387,7 +414,7 @@ int ensure_streams(hase_batch *b)
 // The cached graph for these arguments (captured and instantiated on a miss).
 int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_t *out)
 {
-    int rc = ensure_streams(b);
+    int rc = ensure_streams(b, b->variants.size());
     if (rc) return rc;
     for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
         if (it->n_steps == n_steps && it->act == job.act && it->obs == job.obs &&
@@ -457,6 +484,7 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
     a.walls = b->at<uint8_t>(r.walls);
     a.bb = b->at<uint32_t>(r.bb);
     a.disc = b->at<uint32_t>(r.disc);
+    a.stuck = b->at<uint32_t>(r.stuck);
     a.err = b->at<uint32_t>(r.err);
     a.seed_value = seed;
     a.n_envs = b->n_envs;
@@ -467,7 +495,7 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
 // Mutable per-env state (walls and bitboards never change while stepping).
 struct Snapshot {
     std::vector<uint16_t> pos;
-    std::vector<uint32_t> found, t, ep, steps, disc;
+    std::vector<uint32_t> found, t, ep, steps, stuck, disc;
 };
 
 int snapshot_take(hase_batch *b, Snapshot &s)
@@ -479,6 +507,7 @@ int snapshot_take(hase_batch *b, Snapshot &s)
     s.t.resize(N);
     s.ep.resize(N);
     s.steps.resize(N);
+    s.stuck.resize(N);
     s.disc.resize(p.map_words);
     auto down = [&](void *dst, size_t off, size_t bytes) {
         return hipMemcpyAsync(dst, b->d + off, bytes, hipMemcpyDeviceToHost, b->stream);
@@ -488,6 +517,7 @@ int snapshot_take(hase_batch *b, Snapshot &s)
     HIP_TRY(down(s.t.data(), p.reg.t, 4ull * N));
     HIP_TRY(down(s.ep.data(), p.reg.ep, 4ull * N));
     HIP_TRY(down(s.steps.data(), p.reg.steps, 4ull * N));
+    HIP_TRY(down(s.stuck.data(), p.reg.stuck, 4ull * N));
     if (p.map_words) HIP_TRY(down(s.disc.data(), p.reg.disc, 4ull * p.map_words));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return HASE_OK;
@@ -505,6 +535,7 @@ int snapshot_restore(hase_batch *b, const Snapshot &s)
     HIP_TRY(up(p.reg.t, s.t.data(), 4ull * N));
     HIP_TRY(up(p.reg.ep, s.ep.data(), 4ull * N));
     HIP_TRY(up(p.reg.steps, s.steps.data(), 4ull * N));
+    HIP_TRY(up(p.reg.stuck, s.stuck.data(), 4ull * N));
     if (p.map_words) HIP_TRY(up(p.reg.disc, s.disc.data(), 4ull * p.map_words));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return HASE_OK;
@@ -591,9 +622,16 @@ int hase_create(const hase_batch_desc *desc, void *d_state, uint64_t state_bytes
 
     const uint32_t N = b->n_envs;
     const Plan &p = b->plan;
-    std::vector<uint32_t> s0(N), s1(N), s2(N), id(N);
+    std::vector<uint32_t> s0(N), s1(N), s2(N), id(N), terr(8ull * N, 0u);
     for (uint32_t e = 0; e < N; ++e) {
         const hase_env_spec &s = p.specs[e];
+        if (s.flags & HASE_TERRAIN) {
+            uint32_t *tr = &terr[8ull * e];
+            tr[0] = s.water_pct | ((uint32_t)s.mud_pct << 8) | ((uint32_t)s.stuck_pct << 16);
+            for (int k = 0; k < 9; ++k) tr[1 + k / 4] |= (uint32_t)s.speed_pct[k] << (8 * (k % 4));
+            tr[4] = (uint32_t)s.agent_classes;
+            tr[5] = (uint32_t)(s.agent_classes >> 32);
+        }
         s0[e] = s.height | (s.width << 8) | ((uint32_t)s.n_agents << 16) | ((uint32_t)s.n_seekers << 24);
         s1[e] = s.view_radius | ((uint32_t)s.n_channels << 4) | ((uint32_t)s.flags << 8) |
                 ((uint32_t)s.episode_len << 16);
@@ -613,6 +651,7 @@ int hase_create(const hase_batch_desc *desc, void *d_state, uint64_t state_bytes
         (e = up(p.reg.grid_off, p.grid_off.data(), 4ull * N)) != hipSuccess ||
         (e = up(p.reg.env_id, id.data(), 4ull * N)) != hipSuccess ||
         (e = up(p.reg.map_off, p.map_off.data(), 4ull * N)) != hipSuccess ||
+        (e = up(p.reg.terr, terr.data(), 32ull * N)) != hipSuccess ||
         (e = hipStreamSynchronize(b->stream)) != hipSuccess) {
         delete b;
         return hip_fail(e, "hase_create upload");
@@ -681,7 +720,7 @@ int hase_step_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uin
     const JobDesc job = make_job(b, d_actions, d_obs, d_rew, d_done, d_map);
     if (mode == HASE_STEP_PERSISTENT) return persistent_step(b, job, n_steps);
     if (b->variants.size() > 1) {
-        const int rc = ensure_streams(b);
+        const int rc = ensure_streams(b, b->variants.size());
         if (rc) return rc;
     }
     for (uint32_t k = 0; k < n_steps; ++k) {
@@ -735,6 +774,7 @@ int hase_get_state(hase_batch *b, const hase_host_state *out)
     HIP_TRY(down(out->seed, p.reg.seed, 8ull * N));
     if (out->discovered && p.map_words)
         HIP_TRY(down(out->discovered, p.reg.disc, 4ull * p.map_words));
+    if (out->stuck) HIP_TRY(down(out->stuck, p.reg.stuck, 4ull * N));
     HIP_TRY(hipStreamSynchronize(b->stream));
     for (uint64_t i = 0; i < p.agents; ++i) {
         out->pos_x[i] = (uint8_t)(pos[i] & 0xff);
@@ -761,6 +801,14 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
                             s.height);
             pos[i] = (uint16_t)(in->pos_x[i] | (in->pos_y[i] << 8));
         }
+        const uint8_t max_tile = (s.flags & HASE_TERRAIN) ? 3 : 1;
+        for (uint32_t c = 0; c < (uint32_t)s.height * s.width; ++c)
+            if (in->walls[p.grid_off[e] + c] > max_tile)
+                return fail(HASE_ESTATE, "env %u cell %u: tile value %u above %u", e, c,
+                            in->walls[p.grid_off[e] + c], max_tile);
+        if (in->stuck && in->stuck[e] != 0u &&
+            (!(s.flags & HASE_TERRAIN) || (in->stuck[e] >> s.n_agents) != 0u))
+            return fail(HASE_ESTATE, "env %u: stuck bits of absent agents or without terrain", e);
         if (in->discovered && (s.flags & HASE_EXPLORE)) {
             // map bits past the width are not cells
             const uint32_t rw = (s.width + 31) / 32, tail = s.width & 31u;
@@ -787,6 +835,10 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
         else
             HIP_TRY(hipMemsetAsync(b->d + p.reg.disc, 0, 4ull * p.map_words, b->stream));
     }
+    if (in->stuck)
+        HIP_TRY(up(p.reg.stuck, in->stuck, 4ull * N));
+    else
+        HIP_TRY(hipMemsetAsync(b->d + p.reg.stuck, 0, 4ull * N, b->stream));
     HIP_TRY(launch_init(make_init(b, 0, 1), b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->ready = true;
@@ -909,7 +961,7 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
     struct Group {
         uint32_t lanes = 0, tile0 = 0, n_tiles = 0, slot = 0, map = 0, code0 = 0;
         int kind = KIND_PLAIN;
-        bool mixed = false, xpl = false;
+        bool mixed = false;
     };
     std::vector<Tile> tiles;
     std::vector<Group> groups;
@@ -934,10 +986,9 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
                         tiles.push_back(tl);
                     }
                     g.slot = std::max(g.slot, v.slot_words);
-                    if (v.xpl) g.xpl = true;
+                    g.map = std::max(g.map, v.map_words);
                 }
             }
-            g.map = g.xpl ? g.slot : 0u;
             if ((size_t)(64u / L) * (g.slot + MAX_AGENTS + g.map) * 4 > 65536)
                 return fail(HASE_EINVAL,
                             "requests with %u lanes/env need more than 64 KiB of LDS per wave", L);
@@ -958,7 +1009,7 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
     hase_batch *fb = bs[0];
     const bool fork = groups.size() > 1;
     if (fork) {
-        rc = ensure_streams(fb);
+        rc = ensure_streams(fb, groups.size());
         if (rc) return rc;
         HIP_TRY(hipEventRecord(fb->fork_ev, st));
     }

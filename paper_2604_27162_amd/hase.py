@@ -20,7 +20,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhase.so")
 
 OK, EINVAL, ENOMEM, EGRID, EHIP, ESTATE, ENOTREADY = 0, -1, -2, -3, -4, -5, -6
-COLLIDE, CAPTURE_ENDS, DESYNC, OCCLUDE, EXPLORE = 1, 2, 4, 8, 16
+COLLIDE, CAPTURE_ENDS, DESYNC, OCCLUDE, EXPLORE, TERRAIN = 1, 2, 4, 8, 16, 32
 PERSISTENT, PER_LAUNCH = 0, 1
 N_BUCKETS = 4
 
@@ -36,7 +36,9 @@ class EnvSpec(ctypes.Structure):
                 ("n_agents", ctypes.c_uint8), ("n_seekers", ctypes.c_uint8),
                 ("view_radius", ctypes.c_uint8), ("n_channels", ctypes.c_uint8),
                 ("wall_pct", ctypes.c_uint8), ("flags", ctypes.c_uint8),
-                ("episode_len", ctypes.c_uint16)]
+                ("episode_len", ctypes.c_uint16), ("water_pct", ctypes.c_uint8),
+                ("mud_pct", ctypes.c_uint8), ("stuck_pct", ctypes.c_uint8),
+                ("speed_pct", ctypes.c_uint8 * 9), ("agent_classes", ctypes.c_uint64)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -54,7 +56,8 @@ class HostState(ctypes.Structure):
     _fields_ = [("walls", ctypes.c_void_p), ("pos_x", ctypes.c_void_p),
                 ("pos_y", ctypes.c_void_p), ("found", ctypes.c_void_p), ("t", ctypes.c_void_p),
                 ("episode", ctypes.c_void_p), ("steps", ctypes.c_void_p),
-                ("seed", ctypes.c_void_p), ("discovered", ctypes.c_void_p)]
+                ("seed", ctypes.c_void_p), ("discovered", ctypes.c_void_p),
+                ("stuck", ctypes.c_void_p)]
 
 
 class StepIO(ctypes.Structure):
@@ -120,8 +123,13 @@ def _check(rc: int):
 
 
 def spec_struct(s: dict) -> EnvSpec:
+    """EnvSpec from a spec dict (terrain keys water_pct, mud_pct, stuck_pct,
+    speed (9 values) and classes default to 0, 0, 0, all 100 and 0)."""
+    speed = tuple(int(v) for v in s.get("speed", (100,) * 9))
     return EnvSpec(s["H"], s["W"], s["n"], s["S"], s["r"], s["C"], s["wall_pct"], s["flags"],
-                   s["L"])
+                   s["L"], int(s.get("water_pct", 0)), int(s.get("mud_pct", 0)),
+                   int(s.get("stuck_pct", 0)), (ctypes.c_uint8 * 9)(*speed),
+                   int(s.get("classes", 0)))
 
 
 def make_desc(specs, env_id_base: int = 0):
@@ -245,10 +253,12 @@ class HaseBatch:
                   pos_y=np.zeros(self.agents, np.uint8), found=np.zeros(self.n_envs, np.uint32),
                   t=np.zeros(self.n_envs, np.uint32), episode=np.zeros(self.n_envs, np.uint32),
                   steps=np.zeros(self.n_envs, np.uint32), seed=np.zeros(self.n_envs, np.uint64),
-                  discovered=np.zeros(self.map_words, np.uint32))
+                  discovered=np.zeros(self.map_words, np.uint32),
+                  stuck=np.zeros(self.n_envs, np.uint32))
         hs = HostState(*[st[k].ctypes.data for k in
                          ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")],
-                       st["discovered"].ctypes.data if self.map_words else None)
+                       st["discovered"].ctypes.data if self.map_words else None,
+                       st["stuck"].ctypes.data)
         _check(load().hase_get_state(self._h, ctypes.byref(hs)))
         return st
 
@@ -270,9 +280,15 @@ class HaseBatch:
                 raise ValueError(f"state field discovered has {keep['discovered'].size} entries, "
                                  f"expected {self.map_words}")
             disc = keep["discovered"].ctypes.data
+        stuck = None  # absent: nobody is stuck
+        if st.get("stuck") is not None:
+            keep["stuck"] = np.ascontiguousarray(st["stuck"], dtype=np.uint32).reshape(-1)
+            if keep["stuck"].size != self.n_envs:
+                raise ValueError("state field stuck must have one entry per env")
+            stuck = keep["stuck"].ctypes.data
         hs = HostState(*[keep[k].ctypes.data for k in
                          ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")],
-                       disc)
+                       disc, stuck)
         _check(load().hase_set_state(self._h, ctypes.byref(hs)))
 
     def offsets(self):

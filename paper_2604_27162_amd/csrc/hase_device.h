@@ -163,6 +163,12 @@ __device__ __forceinline__ uint32_t agent_class(uint32_t lo, uint32_t hi, int i)
     return ((i < 16 ? lo : hi) >> (2 * (i & 15))) & 3u;
 }
 
+// a or b as a value. A conditional expression over two variables is an lvalue,
+// which clang may lower to a select of their addresses; with variables that
+// lambdas capture by reference, that kept them (and a table of their
+// addresses) in scratch memory.
+__device__ __forceinline__ uint32_t pick(bool c, uint32_t a, uint32_t b) { return c ? a : b; }
+
 // A uniform word x meets a chance of pct percent: x / 2^32 < pct / 100.
 __device__ __forceinline__ bool chance(uint32_t x, uint32_t pct)
 {
@@ -969,7 +975,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // The step loop, instantiated for channels computed assuming distinct
     // agent cells (collisions on) and for the exact per-agent test; the choice
     // is made once per env, outside the loop.
-    auto run = [&](auto exact_tag, auto feat_tag) {
+    auto run = [&](auto exact_tag, auto feat_tag) __attribute__((always_inline)) {
         constexpr bool EX = decltype(exact_tag)::value;
         // the feature loops (feat_tag = the env kind: exploration, line of
         // sight, or both) are not unrolled (bounded code size); with line of
@@ -1037,8 +1043,24 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 // agent's class may enter and (collisions on) free; then the
                 // move chance and, for a walker entering mud, the stuck chance
                 // decide, from words 2(i&1) and 2(i&1)+1 of the MOVE block of
-                // agent pair i>>1 at this step.
-                U4 blk = {0u, 0u, 0u, 0u};
+                // agent pair i>>1 at this step. Lane l of the env draws the
+                // blocks of pairs l, l + LANES, ...; every lane fetches the
+                // words it needs from their lanes.
+                constexpr int NPAIRS = (NMAX + 1) / 2;
+                constexpr int ROUNDS = (NPAIRS + LANES - 1) / LANES;
+                U4 blk[ROUNDS];
+#pragma unroll
+                for (int rr = 0; rr < ROUNDS; ++rr)
+                    blk[rr] = philox(env, (ST_MOVE << 24) | (uint32_t)(rr * LANES + l), steps, 0u, k0, k1);
+                auto draw = [&](int i, bool second) __attribute__((always_inline)) {
+                    const int k = i >> 1, rr = k / LANES, src = k % LANES;
+                    const U4 b = blk[rr];
+                    const uint32_t w = pick((i & 1) != 0, pick(second, b.w, b.z), pick(second, b.y, b.x));
+                    if constexpr (LANES == 1)
+                        return w;
+                    else
+                        return (uint32_t)__shfl((int)w, q * LANES + src, 64);
+                };
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
                     const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;  // 0 for absent agents
@@ -1054,13 +1076,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                         if (jj != i) occ |= ((uint32_t)(tg ^ pp[jj]) - 1u) >> 31;
                     const bool cand = a != 0u && ((stuck >> i) & 1u) == 0u &&
                                       (class_blocked(cls, b0, b1) & 1u) == 0u && (occ & cmask) == 0u;
-                    if ((i & 1) == 0 && i < n)
-                        blk = philox(env, (ST_MOVE << 24) | (uint32_t)(i >> 1), steps, 0u, k0, k1);
-                    const uint32_t u = (i & 1) ? blk.z : blk.x, v = (i & 1) ? blk.w : blk.y;
+                    const uint32_t u = draw(i, false), v = draw(i, true);
                     const uint32_t type = b0 | (b1 << 1);  // ground, wall, water, mud
                     const uint32_t tile = type == 0u ? 0u : (type == 2u ? 1u : 2u);
                     const uint32_t k = cls * 3u + tile;
-                    const uint32_t pct = ((k < 4u ? sp_a : (k < 8u ? sp_b : sp_c)) >> (8u * (k & 3u))) & 0xffu;
+                    const uint32_t pct = (pick(k < 4u, sp_a, pick(k < 8u, sp_b, sp_c)) >> (8u * (k & 3u))) & 0xffu;
                     const bool go = cand && chance(u, pct);
                     if (go && cls == 0u && type == 3u && chance(v, (tch >> 16) & 0xffu)) stuck |= 1u << i;
                     pp[i] = go ? tg : pp[i];
@@ -1069,18 +1089,21 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 // Chebyshev distance 1 after the moves ((dy + 1) << 8 | (dx + 1)
                 // has both bytes below 3 exactly then)
                 const uint32_t before = stuck;
+                if (before != 0u) {
+                    const uint32_t smask = (1u << S) - 1u;  // seekers; hmask: hiders
 #pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    bool freed = false;
+                    for (int i = 0; i < NMAX; ++i) {
+                        uint32_t nb = 0u;  // agents within Chebyshev distance 1 of i
 #pragma unroll
-                    for (int jj = 0; jj < NMAX; ++jj) {
-                        if (jj == i) continue;
-                        const uint32_t du = (uint32_t)(pp[i] - pp[jj]) + 257u;
-                        const uint32_t lo = du & 0xffu, hi = du >> 8;
-                        const bool near = (lo > hi ? lo : hi) < 3u;
-                        freed |= jj < n && (jj < S) == (i < S) && near && ((before >> jj) & 1u) == 0u;
+                        for (int jj = 0; jj < NMAX; ++jj) {
+                            if (jj == i) continue;
+                            const uint32_t du = (uint32_t)(pp[i] - pp[jj]) + 257u;
+                            const uint32_t lo = du & 0xffu, hi = du >> 8;
+                            nb |= (lo > hi ? lo : hi) < 3u ? 1u << jj : 0u;
+                        }
+                        const uint32_t mates = (i < S ? smask : hmask) & ~(1u << i);
+                        stuck &= (nb & mates & ~before) != 0u ? ~(1u << i) : 0xffffffffu;
                     }
-                    if (freed) stuck &= ~(1u << i);
                 }
             } else if constexpr (NBR) {
                 // Integer decisions only: lane-mask logic would cost a round

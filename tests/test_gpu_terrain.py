@@ -171,3 +171,39 @@ def test_full_size_terrain4k_sampled():
     g.close()
     del out
     torch.cuda.empty_cache()
+
+
+EDGE = {
+    "max_agents_64x64": wl.with_terrain(wl.spec(64, 64, 20, 4, 4, 10), 20, 15, 40,
+                                        (100, 0, 50, 0, 90, 0, 70, 70, 70),
+                                        [i % 3 for i in range(20)]),
+    "tiny_3x3_flyers": wl.with_terrain(wl.spec(3, 3, 2, 1, 4, 0, L=9), 40, 40, 100, (100,) * 9,
+                                       [wl.FLYER, wl.FLYER]),
+    "nobody_moves": wl.with_terrain(wl.spec(16, 16, 4, 2, 3, 10), 20, 20, 50, (0,) * 9,
+                                    [0, 1, 2, 0]),
+    "always_stuck_walkers": wl.with_terrain(wl.spec(16, 16, 6, 3, 3, 5), 10, 60, 100, (100,) * 9,
+                                            [wl.WALKER] * 6),
+}
+
+
+@pytest.mark.parametrize("name", list(EDGE))
+def test_terrain_edge_specs(name):
+    run_pair([EDGE[name]] * 67, seed=12, steps=180)
+
+
+def test_one_lane_per_env_terrain():
+    """Two tile planes per env at one lane per env fit small boards."""
+    specs = random_terrain_specs(140, 12, base="small")
+    run_pair(specs, seed=29, steps=150, lanes=[1, 1, 4, 8])
+
+
+def test_reset_refuses_a_class_without_room():
+    sp = wl.with_terrain(wl.spec(8, 8, 3, 1, 3, 0), 0, 30, 0, (100,) * 9,
+                         [wl.WALKER, wl.SWIMMER, wl.FLYER])
+    g = hase.HaseBatch([wl.spec(8, 8, 2, 1, 3, 0), sp], device=DEV)
+    with pytest.raises(hase.HaseError) as ei:
+        g.reset(3)
+    assert ei.value.code == hase.EGRID
+    with pytest.raises(ValueError):
+        o.OracleBatch([wl.spec(8, 8, 2, 1, 3, 0), sp]).reset(3)
+    g.close()

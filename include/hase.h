@@ -42,7 +42,7 @@ extern "C" {
 #define HASE_OK 0
 #define HASE_EINVAL (-1)  /* bad spec or argument */
 #define HASE_ENOMEM (-2)  /* caller's state buffer smaller than required */
-#define HASE_EGRID (-3)   /* an env drew fewer free cells than agents */
+#define HASE_EGRID (-3)   /* an env drew too few free cells for its agents */
 #define HASE_EHIP (-4)    /* HIP runtime error (detail in hase_last_error) */
 #define HASE_ESTATE (-5)  /* state arrays inconsistent with the batch */
 #define HASE_ENOTREADY (-6) /* step/observe before the first reset or set_state */
@@ -217,9 +217,11 @@ int hase_get_map_offsets(const hase_batch *b, uint64_t *h_map_off);
 
 /*
  * reset(seed) of every env (Sec. 3.3 desynchronised start, Sec. 4.2 grid):
- * walls from the generator, free-cell check (HASE_EGRID names the first env
- * with fewer free cells than agents), agents spawned, counters cleared,
- * desync offset drawn; writes the first observation to d_obs0
+ * walls (terrain: tile types) from the generator, free-cell check (HASE_EGRID
+ * names the first env with fewer free cells than agents, or with terrain,
+ * fewer than n cells some agent's class may stand on), agents spawned,
+ * counters, stuck agents and discovery maps cleared, desync offset drawn;
+ * writes the first observation to d_obs0
  * (obs_words_per_step words; may be NULL). Synchronises the stream.
  */
 int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0);

@@ -692,7 +692,7 @@ int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0)
     HIP_TRY(hipStreamSynchronize(b->stream));
     if (err != 0xffffffffu) {
         b->ready = false;
-        return fail(HASE_EGRID, "env %u has fewer free cells than agents", err);
+        return fail(HASE_EGRID, "env %u has too few free cells for its agents", err);
     }
     b->ready = true;
     if (d_obs0) {
@@ -1053,7 +1053,7 @@ const char *hase_strerror(int code)
     case HASE_OK: return "ok";
     case HASE_EINVAL: return "invalid argument";
     case HASE_ENOMEM: return "state buffer too small";
-    case HASE_EGRID: return "an environment has fewer free cells than agents";
+    case HASE_EGRID: return "an environment has too few free cells for its agents";
     case HASE_EHIP: return "HIP runtime error";
     case HASE_ESTATE: return "inconsistent state";
     case HASE_ENOTREADY: return "batch not reset";

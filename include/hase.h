@@ -278,9 +278,12 @@ int hase_set_state(hase_batch *b, const hase_host_state *in);
  * Tiling of the step kernel: lanes_per_env in {1,2,4,8,16} lanes of one
  * 64-lane wavefront cooperate on one env, so a wave steps 64/lanes_per_env
  * envs. lanes[v] applies to the envs whose agent count falls in bucket v:
- * v = 0 for n <= 2, 1 for n <= 4, 2 for n <= 10, 3 for n <= 20. 0 keeps the
- * built-in default. Results never depend on the tiling. Rebuilds the tile
- * table (synchronously) and drops cached graphs.
+ * v = 0 for n <= 2, 1 for n <= 4, 2 for n <= 10, 3 for n <= 20. 0 takes the
+ * default: 4, 4, 16, 16 lanes, except that when the buckets with the widest
+ * of those hold at least half of the batch's agents, every bucket present
+ * takes the widest (one launch group); hase_create starts from the
+ * default. Results never depend on the tiling. Rebuilds the tile table
+ * (synchronously) and drops cached graphs.
  */
 #define HASE_N_BUCKETS 4
 int hase_set_tiling(hase_batch *b, const uint32_t lanes[HASE_N_BUCKETS]);

@@ -77,8 +77,8 @@ extern "C" {
  * chance; a walker entering mud gets stuck with the stuck chance; a stuck
  * agent does not move until, after the moves of a step, a teammate that is
  * not stuck stands within Chebyshev distance 1. Observation channel 0 holds
- * the tiles the agent's class may not enter. Not combinable with
- * HASE_OCCLUDE (HASE_EINVAL). */
+ * the tiles the agent's class may not enter. With HASE_OCCLUDE, only walls
+ * and cells outside the map block sight. */
 #define HASE_TERRAIN 32u
 
 /* step modes */

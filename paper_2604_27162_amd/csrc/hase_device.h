@@ -203,11 +203,13 @@ __device__ __forceinline__ void wave_lds_fence()
 // Window rows of one agent into W-word bitmasks (bit k = row * D + column),
 // fully unrolled for radius R: wall|outside from the padded board (TER: the
 // cells the agent's class cls may not enter, from the two tile planes, plane
-// 1 pw words after plane 0) and, for 4-channel envs, outside-the-map only.
+// 1 pw words after plane 0, and, when lw is given, the walls and outside
+// alone, which block sight) and, for 4-channel envs, outside-the-map only.
 template <int R, int W, bool TER = false>
 __device__ __forceinline__ void window_rows(const uint32_t *slot, int H, int Wd, int ax, int ay,
                                             bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
-                                            int pw = 0, uint32_t cls = 0u)
+                                            int pw = 0, uint32_t cls = 0u,
+                                            uint32_t (*lw)[W] = nullptr)
 {
     constexpr int D = 2 * R + 1;
     constexpr uint32_t DM = (1u << D) - 1u;
@@ -219,10 +221,17 @@ __device__ __forceinline__ void window_rows(const uint32_t *slot, int H, int Wd,
     for (int rho = 0; rho < D; ++rho) {
         const uint32_t *rp = base + rho * LDS_ROW;
         uint32_t bits = __builtin_amdgcn_alignbit(rp[1], rp[0], sh);
-        if constexpr (TER)
-            bits = class_blocked(cls, bits, __builtin_amdgcn_alignbit(rp[pw + 1], rp[pw], sh));
-        bits &= DM;
         const int off = rho * D, wi = off >> 5, b = off & 31;
+        if constexpr (TER) {
+            const uint32_t b1 = __builtin_amdgcn_alignbit(rp[pw + 1], rp[pw], sh);
+            if (lw != nullptr) {
+                const uint32_t wb = bits & ~b1 & DM;  // wall type (outside reads as wall)
+                (*lw)[wi] |= wb << b;
+                if (b + D > 32) (*lw)[wi + 1] |= wb >> (32 - b);
+            }
+            bits = class_blocked(cls, bits, b1);
+        }
+        bits &= DM;
         wall[wi] |= bits << b;
         if (b + D > 32) wall[wi + 1] |= bits >> (32 - b);
     }
@@ -327,14 +336,18 @@ __device__ __forceinline__ int agent_masks_raw(const uint32_t *slot, int H, int 
                                            const int (&pp)[NMAX], int a, int pa, int n, int S,
                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
                                            uint32_t (&team)[W], uint32_t (&opp)[W], int pw = 0,
-                                           uint32_t cls = 0u)
+                                           uint32_t cls = 0u, uint32_t (*lw)[W] = nullptr)
 {
     constexpr int D = 2 * R + 1;
     constexpr int CENTER = R * D + R;
 #pragma unroll
     for (int i = 0; i < W; ++i) wall[i] = outm[i] = team[i] = opp[i] = 0u;
+    if (lw != nullptr) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) (*lw)[i] = 0u;
+    }
     const int ax = pa & 0xff, ay = pa >> 8;
-    window_rows<R, W, TER>(slot, H, Wd, ax, ay, want_out, wall, outm, pw, cls);
+    window_rows<R, W, TER>(slot, H, Wd, ax, ay, want_out, wall, outm, pw, cls, lw);
     const bool sa = a < S;
     if constexpr (!EXACT && NMAX <= 4) {
         // Distinct cells: the agent itself is the centre (in no channel) and
@@ -556,14 +569,15 @@ __device__ __forceinline__ void los_visible(const uint32_t (&wall)[W], uint32_t 
 }
 
 // Line of sight: the channels of one agent restricted to the cells visible
-// from its own (vis, from the wall|outside window), and the count of the
-// visible opponents.
+// from its own (vis, from the window of sight blockers: walls and outside),
+// and the count of the visible opponents.
 template <int R, int W, int NMAX, bool EXACT>
 __device__ __forceinline__ int occlude(const int (&pp)[NMAX], int a, int pa, int n, int S,
-                                       uint32_t (&wall)[W], uint32_t (&outm)[W], uint32_t (&team)[W],
+                                       const uint32_t (&blockers)[W], uint32_t (&wall)[W],
+                                       uint32_t (&outm)[W], uint32_t (&team)[W],
                                        uint32_t (&opp)[W], uint32_t (&vis)[W])
 {
-    los_visible<R, W>(wall, vis);
+    los_visible<R, W>(blockers, vis);
 #pragma unroll
     for (int i = 0; i < W; ++i) {
         wall[i] &= vis[i];
@@ -611,15 +625,24 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
                                            uint32_t cls)
 {
     // exploration needs the outside-the-map cells whatever the channel count
-    // (outm is stored only for 4-channel envs)
+    // (outm is stored only for 4-channel envs); with terrain and line of
+    // sight, only walls and outside block sight, not what the class may not
+    // enter
+    uint32_t lw[W];
     int cnt = agent_masks_raw<R, W, NMAX, EXACT, TER>(slot, H, Wd, pp, a, pa, n, S,
                                                       FEAT ? (want_out || xpl) : want_out, wall,
-                                                      outm, team, opp, pw, cls);
+                                                      outm, team, opp, pw, cls,
+                                                      (TER && occl) ? &lw : nullptr);
     if constexpr (FEAT) {
         uint32_t vis[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) vis[i] = 0xffffffffu;
-        if (occl) cnt = occlude<R, W, NMAX, EXACT>(pp, a, pa, n, S, wall, outm, team, opp, vis);
+        if (occl) {
+            if constexpr (TER)
+                cnt = occlude<R, W, NMAX, EXACT>(pp, a, pa, n, S, lw, wall, outm, team, opp, vis);
+            else
+                cnt = occlude<R, W, NMAX, EXACT>(pp, a, pa, n, S, wall, wall, outm, team, opp, vis);
+        }
 #pragma unroll
         for (int i = 0; i < W; ++i) seen[i] = vis[i] & ~outm[i];
     }

@@ -107,8 +107,8 @@ struct InitArgs {
 constexpr int KIND_PLAIN = 0;    // no line of sight, no exploration, no terrain
 constexpr int KIND_EXPLORE = 1;  // bit 0: exploration
 constexpr int KIND_LOS = 2;      // bit 1: line of sight
-constexpr int KIND_TERRAIN = 4;  // bit 2: terrain (never with line of sight)
-constexpr int N_KINDS = 6;       // kinds 0..5
+constexpr int KIND_TERRAIN = 4;  // bit 2: terrain
+constexpr int N_KINDS = 8;       // kinds 0..7
 inline int env_kind(uint32_t flags)
 {
     return ((flags & 8u) ? KIND_LOS : 0) | ((flags & 16u) ? KIND_EXPLORE : 0) |
@@ -136,7 +136,7 @@ hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 // Per-lanes entry points, one translation unit each: single-variant and
 // mixed plain kernels (hase_step_l<L>.hip, hase_mixed_l<L>.hip), the line of
 // sight and exploration kinds (hase_feat_l<L>.hip) and the terrain kinds
-// (hase_terr_l<L>.hip).
+// (hase_terr_l<L>.hip, with line of sight hase_terrlos_l<L>.hip).
 #define HASE_DECLARE_LANES(L)                                                                     \
     hipError_t launch_step_lanes##L(int nmax, int r, const Tile *tiles, uint32_t n_tiles,        \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
@@ -152,7 +152,11 @@ hipError_t launch_init(const InitArgs &a, hipStream_t stream);
     hipError_t launch_terr_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,               \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
                                     uint32_t step_base, uint32_t slot_words, uint32_t map_words,  \
-                                    hipStream_t stream);
+                                    hipStream_t stream);                                          \
+    hipError_t launch_terrlos_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,            \
+                                       const JobDesc *jobs, const JobDesc &job0, uint32_t K,      \
+                                       uint32_t step_base, uint32_t slot_words,                   \
+                                       uint32_t map_words, hipStream_t stream);
 HASE_DECLARE_LANES(1)
 HASE_DECLARE_LANES(2)
 HASE_DECLARE_LANES(4)

@@ -107,8 +107,6 @@ int check_spec(const hase_env_spec &s, uint32_t idx)
     if (s.flags & ~63u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
     if (s.episode_len < 1) return fail(HASE_EINVAL, "spec %u: episode_len must be >= 1", idx);
     if (s.flags & HASE_TERRAIN) {
-        if (s.flags & HASE_OCCLUDE)
-            return fail(HASE_EINVAL, "spec %u: terrain with line of sight is not supported", idx);
         if ((int)s.wall_pct + s.water_pct + s.mud_pct > 99)
             return fail(HASE_EINVAL, "spec %u: wall_pct + water_pct + mud_pct must be <= 99", idx);
         if (s.stuck_pct > 100) return fail(HASE_EINVAL, "spec %u: stuck_pct must be <= 100", idx);

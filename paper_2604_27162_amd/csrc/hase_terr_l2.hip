@@ -1,5 +1,6 @@
 // Mixed-variant step kernels with 2 lanes per environment for the terrain
-// kinds: terrain alone and with exploration (one kernel each).
+// kinds: terrain alone and with exploration (one kernel each); the kinds
+// with line of sight are in hase_terrlos_l2.hip.
 #include "hase_device.h"
 
 namespace hase {
@@ -15,6 +16,10 @@ hipError_t launch_terr_lanes2(int kind, const Tile *tiles, uint32_t n_tiles, con
     case KIND_TERRAIN | KIND_EXPLORE:
         return launch_mixed_l<2, KIND_TERRAIN | KIND_EXPLORE>(tiles, n_tiles, jobs, job0, K, step_base,
                                                               slot_words, map_words, stream);
+    case KIND_TERRAIN | KIND_LOS:
+    case KIND_TERRAIN | KIND_LOS | KIND_EXPLORE:
+        return launch_terrlos_lanes2(kind, tiles, n_tiles, jobs, job0, K, step_base, slot_words,
+                                     map_words, stream);
     default: return hipErrorInvalidValue;
     }
 }

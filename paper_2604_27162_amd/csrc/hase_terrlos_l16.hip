@@ -1,0 +1,22 @@
+// Mixed-variant step kernels with 16 lanes per environment for terrain with
+// line of sight, without and with exploration (one kernel each).
+#include "hase_device.h"
+
+namespace hase {
+
+hipError_t launch_terrlos_lanes16(int kind, const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
+                                  const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
+                                  uint32_t map_words, hipStream_t stream)
+{
+    switch (kind) {
+    case KIND_TERRAIN | KIND_LOS:
+        return launch_mixed_l<16, KIND_TERRAIN | KIND_LOS>(tiles, n_tiles, jobs, job0, K, step_base,
+                                                           slot_words, map_words, stream);
+    case KIND_TERRAIN | KIND_LOS | KIND_EXPLORE:
+        return launch_mixed_l<16, KIND_TERRAIN | KIND_LOS | KIND_EXPLORE>(tiles, n_tiles, jobs, job0, K, step_base,
+                                                                          slot_words, map_words, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hase

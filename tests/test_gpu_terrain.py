@@ -39,16 +39,30 @@ def test_terrain_with_exploration():
     run_maps(specs, seed=17, steps=200)
 
 
+@pytest.mark.parametrize("mode", [hase.PERSISTENT, hase.PER_LAUNCH])
+def test_terrain_with_line_of_sight(mode):
+    """Only walls and outside block sight; water and mud do not."""
+    specs = [dict(s, flags=s["flags"] | wl.OCCLUDE) for s in random_terrain_specs(257, 13)]
+    run_pair(specs, seed=19, steps=200, mode=mode)
+
+
+def test_terrain_with_line_of_sight_and_exploration():
+    specs = [dict(s, flags=s["flags"] | wl.OCCLUDE | wl.EXPLORE)
+             for s in random_terrain_specs(199, 14)]
+    run_maps(specs, seed=21, steps=180)
+
+
 @pytest.mark.parametrize("lanes", [4, 8, 16])
 def test_every_kind_in_one_batch(lanes):
-    """Plain, exploring, occluding, both, terrain and terrain + exploration
-    envs interleaved (fewer than 4 lanes per env would not fit two 64-row
-    tile planes and a discovery map per env in one wave's LDS)."""
-    ter = random_terrain_specs(300, 9)
-    extra = [0, wl.EXPLORE, wl.OCCLUDE, wl.EXPLORE | wl.OCCLUDE, None, wl.EXPLORE]
+    """All eight env kinds interleaved: plain, exploring, occluding, both,
+    and the same four with terrain (fewer than 4 lanes per env would not fit
+    two 64-row tile planes and a discovery map per env in one wave's LDS)."""
+    ter = random_terrain_specs(320, 9)
+    extra = [0, wl.EXPLORE, wl.OCCLUDE, wl.EXPLORE | wl.OCCLUDE, None, wl.EXPLORE, wl.OCCLUDE,
+             wl.OCCLUDE | wl.EXPLORE]
     specs = []
     for i, s in enumerate(ter):
-        k = i % 6
+        k = i % 8
         if k < 4:
             base = {f: s[f] for f in ("H", "W", "n", "S", "r", "C", "wall_pct", "flags", "L")}
             base["flags"] &= ~wl.TERRAIN

@@ -83,6 +83,9 @@ MUTATIONS = {
     "terrain_obs_ignores_class": (
         "if (!inb || !or_enterable(walls[cy * W + cx], cls)) oi[0 * w + word] |= bit;",
         "if (!inb || walls[cy * W + cx] == OR_WALL) oi[0 * w + word] |= bit;"),
+    "terrain_water_blocks_sight": (
+        "int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx] == OR_WALL;",
+        "int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx] != OR_GROUND;"),
     "terrain_stuck_kept_at_auto_reset": (
         "        b->found[e] = 0;\n        b->stuck[e] = 0;\n        if (flags & OR_EXPLORE)",
         "        b->found[e] = 0;\n        if (flags & OR_EXPLORE)"),

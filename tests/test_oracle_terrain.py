@@ -91,6 +91,10 @@ def check_reduces_to_plain(libpath=None, n_envs=40, steps=150):
     # the terrain map has water and mud where the plain map is open ground
     assert np.array_equal(sa["walls"] == WALL, sb["walls"] == WALL)
     assert (sb["walls"] == WATER).any() and (sb["walls"] == MUD).any()
+    # with line of sight too: water and mud do not block sight
+    occ = [dict(s, flags=s["flags"] | 8) for s in plain]
+    occ_flyers = [dict(s, flags=s["flags"] | 8) for s in flyers]
+    compare_runs(occ, occ_flyers, 15, steps, libpath)
 
 
 def test_reduces_to_plain():

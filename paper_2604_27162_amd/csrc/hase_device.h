@@ -154,7 +154,10 @@ __device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, cons
 // cls may not enter, from plane bits b0, b1 (any width of bits at once).
 __device__ __forceinline__ uint32_t class_blocked(uint32_t cls, uint32_t b0, uint32_t b1)
 {
-    return cls == 0u ? (b0 ^ b1) : (cls == 1u ? (b0 | ~b1) : (b0 & ~b1));
+    // masks, not a conditional: the compiler turned the three-way choice on
+    // a per-lane class into branches
+    const uint32_t m0 = 0u - (cls == 0u ? 1u : 0u), m1 = 0u - (cls == 1u ? 1u : 0u);
+    return ((b0 ^ b1) & m0) | ((b0 | ~b1) & m1) | ((b0 & ~b1) & ~(m0 | m1));
 }
 
 // Class of agent i from the two class words (2 bits per agent).
@@ -1097,15 +1100,19 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 #pragma unroll
                     for (int jj = 0; jj < NMAX; ++jj)
                         if (jj != i) occ |= ((uint32_t)(tg ^ pp[jj]) - 1u) >> 31;
-                    const bool cand = a != 0u && ((stuck >> i) & 1u) == 0u &&
-                                      (class_blocked(cls, b0, b1) & 1u) == 0u && (occ & cmask) == 0u;
+                    // every condition evaluated, combined with bitwise ops:
+                    // short-circuit && compiles to a branch per agent here
+                    const uint32_t blocked = ((stuck >> i) & 1u) | (class_blocked(cls, b0, b1) & 1u) |
+                                             (occ & cmask) | (a == 0u ? 1u : 0u);
                     const uint32_t u = draw(i, false), v = draw(i, true);
                     const uint32_t type = b0 | (b1 << 1);  // ground, wall, water, mud
-                    const uint32_t tile = type == 0u ? 0u : (type == 2u ? 1u : 2u);
+                    const uint32_t tile = (type + 1u) >> 1;  // ground 0, water 1, mud 2 (wall: blocked)
                     const uint32_t k = cls * 3u + tile;
                     const uint32_t pct = (pick(k < 4u, sp_a, pick(k < 8u, sp_b, sp_c)) >> (8u * (k & 3u))) & 0xffu;
-                    const bool go = cand && chance(u, pct);
-                    if (go && cls == 0u && type == 3u && chance(v, (tch >> 16) & 0xffu)) stuck |= 1u << i;
+                    const uint32_t go = (chance(u, pct) ? 1u : 0u) & (blocked ^ 1u);
+                    const uint32_t sticks = go & (cls == 0u ? 1u : 0u) & (type == 3u ? 1u : 0u) &
+                                            (chance(v, (tch >> 16) & 0xffu) ? 1u : 0u);
+                    stuck |= sticks << i;
                     pp[i] = go ? tg : pp[i];
                 }
                 // rescue: freed by a teammate that is not stuck within
@@ -1114,18 +1121,24 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 const uint32_t before = stuck;
                 if (before != 0u) {
                     const uint32_t smask = (1u << S) - 1u;  // seekers; hmask: hiders
+                    uint32_t nb[NMAX];  // agents within Chebyshev distance 1 of each
+#pragma unroll
+                    for (int i = 0; i < NMAX; ++i) nb[i] = 0u;
 #pragma unroll
                     for (int i = 0; i < NMAX; ++i) {
-                        uint32_t nb = 0u;  // agents within Chebyshev distance 1 of i
 #pragma unroll
-                        for (int jj = 0; jj < NMAX; ++jj) {
-                            if (jj == i) continue;
+                        for (int jj = i + 1; jj < NMAX; ++jj) {
                             const uint32_t du = (uint32_t)(pp[i] - pp[jj]) + 257u;
                             const uint32_t lo = du & 0xffu, hi = du >> 8;
-                            nb |= (lo > hi ? lo : hi) < 3u ? 1u << jj : 0u;
+                            const uint32_t near = (lo > hi ? lo : hi) < 3u ? 1u : 0u;
+                            nb[i] |= near << jj;
+                            nb[jj] |= near << i;
                         }
+                    }
+#pragma unroll
+                    for (int i = 0; i < NMAX; ++i) {
                         const uint32_t mates = (i < S ? smask : hmask) & ~(1u << i);
-                        stuck &= (nb & mates & ~before) != 0u ? ~(1u << i) : 0xffffffffu;
+                        stuck &= (nb[i] & mates & ~before) != 0u ? ~(1u << i) : 0xffffffffu;
                     }
                 }
             } else if constexpr (NBR) {

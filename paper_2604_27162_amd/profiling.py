@@ -7,7 +7,7 @@ Runs (each as a child process of this one, which never touches the GPU):
   2. rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, over bench.py;
   3. the same two counters over bench.py --copy-probe (a plain device copy
      of known size) to calibrate them: scale = true bytes / counted bytes.
-Raw output goes to --raw (default gpurun_out/profile_<workload>); the summary
+Raw output goes to --raw (default rocprof_raw/profile_<workload>); the summary
 (--summarize-only can redo it from raw output copied back from the GPU
 machine) to profiles/step_kernel_<workload>.md and the HBM
 traffic per launch to profiles/traffic.json, keyed by the hash of the device
@@ -57,7 +57,7 @@ def main(argv=None):
     ap.add_argument("--summarize-only", action="store_true",
                     help="only summarise raw output collected earlier")
     args = ap.parse_args(argv)
-    raw = os.path.abspath(args.raw or os.path.join(ROOT, "gpurun_out", f"profile_{args.workload}"))
+    raw = os.path.abspath(args.raw or os.path.join(ROOT, "rocprof_raw", f"profile_{args.workload}"))
     os.makedirs(raw, exist_ok=True)
     os.makedirs(args.out, exist_ok=True)
     py = sys.executable

@@ -242,3 +242,15 @@ def test_full_size_explore16k_sampled():
     g.close()
     del go, gr, gd, gm
     torch.cuda.empty_cache()
+
+
+def test_odd_map_shapes():
+    """Map outputs whose word count is not a multiple of 4 (ragged 16-byte
+    chunks) and rows of two words whose second word is nearly empty."""
+    shapes = [(7, 45, 2, 2), (9, 33, 3, 3), (5, 2, 1, 1), (11, 64, 4, 4), (3, 31, 2, 1)]
+    specs = []
+    for i in range(60):
+        H, W, n, r = shapes[i % len(shapes)]
+        specs.append(dict(wl.spec(H, W, n, r, 3 + (i % 2), 5, L=40), flags=wl.DEFAULT_FLAGS |
+                          wl.EXPLORE | (wl.OCCLUDE if i % 3 == 0 else 0)))
+    run_maps(specs, seed=37, steps=120, lanes=[2, 4, 8, 16])

@@ -19,7 +19,9 @@
  *   - environments are desynchronised at initialisation (Sec. 3.3, last
  *     paragraph);
  *   - each agent receives a decentralised observation of its own local
- *     window (Sec. 3.3, observability mode 1).
+ *     window (Sec. 3.3, observability mode 1);
+ *   - optionally (OR_RADIO) agents send their beliefs about the hiders to a
+ *     chosen agent by radio (Sec. 3.3, radio paragraph).
  * Readings where the paper is silent are listed in the header comment of each
  * function and in the design notes; every one binds the GPU path as well.
  *
@@ -42,12 +44,14 @@
 #define OR_OCCLUDE 8u
 #define OR_EXPLORE 16u
 #define OR_TERRAIN 32u
+#define OR_RADIO 64u
 
 #define OR_STREAM_ACTION 0u
 #define OR_STREAM_SPAWN 1u
 #define OR_STREAM_WALL 2u
 #define OR_STREAM_DESYNC 3u
 #define OR_STREAM_MOVE 4u
+#define OR_STREAM_RADIO 5u
 
 #define OR_SPAWN_ATTEMPTS 64
 
@@ -78,7 +82,7 @@ typedef struct {
     const int64_t *agent_off; /* [n_envs] first agent of env e in px/py/rew/actions */
     const int64_t *obs_off;   /* [n_envs] first obs word of env e in one step's obs */
     int64_t agents_total;     /* sum of n over envs */
-    int64_t obs_total;        /* sum of n*C*w over envs */
+    int64_t obs_total;        /* sum of n*(C*w + radio) over envs */
     uint8_t *walls;           /* [sum H*W] 1 = blocking tile */
     uint8_t *px, *py;         /* [agents_total] */
     uint32_t *found, *t, *ep, *steps; /* [n_envs] */
@@ -88,6 +92,7 @@ typedef struct {
     int64_t disc_total;       /* sum of map words over envs */
     uint32_t *disc;           /* [disc_total] discovery maps (OR_EXPLORE envs) */
     uint32_t *stuck;          /* [n_envs] bit i: agent i is stuck (OR_TERRAIN envs) */
+    uint32_t *belief;         /* [agents_total] bit h: the agent knows of hider h (OR_RADIO) */
 } or_batch;
 
 /* ---------------------------------------------------------------- Philox */
@@ -153,6 +158,13 @@ static int or_words(int r)
 }
 
 static int or_is_seeker(int i, int S) { return i < S; }
+
+/* Observation words of one agent: C channels of or_words(r) words, then,
+ * with OR_RADIO, one belief word (reading R29). */
+static int or_agent_obs_words(const int32_t *sp)
+{
+    return sp[SP_C] * or_words(sp[SP_R]) + (((uint32_t)sp[SP_FLAGS] & OR_RADIO) ? 1 : 0);
+}
 
 /* Discovery map of an OR_EXPLORE env: H rows of ceil(W/32) words, cell (x,y)
  * at bit x & 31 of word y * ceil(W/32) + x / 32; 0 words for other envs. */
@@ -299,16 +311,19 @@ static void or_spawn(const int32_t *sp, const uint8_t *walls, uint8_t *px, uint8
  * OR_TERRAIN: a tile the agent's class may not enter, or outside), 1
  * teammate (another agent of the same role), 2 opponent, 3 (only when C = 4)
  * outside the map. Layout [agent][channel][word]. With OR_OCCLUDE, a window
- * cell not visible from the agent (or_visible) reads 0 in every channel. */
+ * cell not visible from the agent (or_visible) reads 0 in every channel.
+ * With OR_RADIO each agent's words end with its belief word (the 1-D
+ * belief vector of the observation space, Sec. 3.1, reading R29). */
 static void or_observe(const int32_t *sp, const uint8_t *walls, const uint8_t *px,
-                       const uint8_t *py, uint32_t *obs)
+                       const uint8_t *py, const uint32_t *belief, uint32_t *obs)
 {
     int H = sp[SP_H], W = sp[SP_W], n = sp[SP_N], S = sp[SP_S], r = sp[SP_R], C = sp[SP_C];
     int occlude = ((uint32_t)sp[SP_FLAGS] & OR_OCCLUDE) != 0;
-    int d = 2 * r + 1, w = or_words(r);
-    memset(obs, 0, sizeof(uint32_t) * (size_t)(n * C * w));
+    int d = 2 * r + 1, w = or_words(r), aw = or_agent_obs_words(sp);
+    memset(obs, 0, sizeof(uint32_t) * (size_t)(n * aw));
     for (int i = 0; i < n; ++i) {
-        uint32_t *oi = obs + (size_t)i * C * w;
+        uint32_t *oi = obs + (size_t)i * aw;
+        if ((uint32_t)sp[SP_FLAGS] & OR_RADIO) oi[aw - 1] = belief[i];
         int cls = or_class(sp, i);
         for (int dy = -r; dy <= r; ++dy) {
             for (int dx = -r; dx <= r; ++dx) {
@@ -382,7 +397,8 @@ int or_reset(or_batch *b, uint64_t seed, uint32_t *obs0)
             b->t[e] = or_range(or_draw(seed, env, OR_STREAM_DESYNC, 0, 0, 0, 0), (uint32_t)sp[SP_L]);
         else
             b->t[e] = 0;
-        if (obs0) or_observe(sp, walls, px, py, obs0 + b->obs_off[e]);
+        for (int i = 0; i < n; ++i) b->belief[b->agent_off[e] + i] = 0;
+        if (obs0) or_observe(sp, walls, px, py, b->belief + b->agent_off[e], obs0 + b->obs_off[e]);
     }
     return 0;
 }
@@ -393,7 +409,7 @@ void or_observe_all(or_batch *b, uint32_t *obs)
     for (int e = 0; e < b->n_envs; ++e) {
         const int32_t *sp = b->spec + (size_t)e * SP_FIELDS;
         or_observe(sp, b->walls + b->grid_off[e], b->px + b->agent_off[e],
-                   b->py + b->agent_off[e], obs + b->obs_off[e]);
+                   b->py + b->agent_off[e], b->belief + b->agent_off[e], obs + b->obs_off[e]);
     }
 }
 
@@ -404,7 +420,10 @@ static const int OR_DY[5] = { 0, -1, 1, 0, 0 };
 
 /* One step of one env, in this order (reading of the step loop of Sec. 4.1):
  *   1 actions: external value if given and not -1, else the ACTION draw at
- *     this env's step count; values outside 0..4 mean stay;
+ *     this env's step count; values outside 0..4 mean stay; with OR_RADIO a
+ *     drawn action also draws a radio target (the RADIO draw, uniform over
+ *     the n agents, itself meaning no message) and an external value v >= 0
+ *     is move v mod 5 plus target v div 5 - 1 (v div 5 = 0 or > n: none);
  *   2 moves in agent-index order; a move is rejected if it leaves the map,
  *     enters a blocking tile, or (collisions on) enters a cell held by any
  *     other agent at that moment (agents < i already moved, agents > i not);
@@ -421,8 +440,9 @@ static const int OR_DY[5] = { 0, -1, 1, 0, 0 };
  *   4 t += 1; terminated = capture rule on, at least one hider, every hider
  *     found; truncated = t >= L; done = terminated | truncated << 1;
  *   3b exploration reward and discovery map (OR_EXPLORE);
- *   5 if done: next episode, t = 0, Found and stuck cleared, agents respawned,
- *     grid kept, discovery map cleared;
+ *   3c radio messages (OR_RADIO);
+ *   5 if done: next episode, t = 0, Found, stuck and beliefs cleared, agents
+ *     respawned, grid kept, discovery map cleared;
  *   6 step count += 1;
  *   7 observation of the (possibly new) state.
  */
@@ -437,16 +457,27 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
     uint8_t *px = b->px + b->agent_off[e], *py = b->py + b->agent_off[e];
     uint64_t seed = b->seed[e];
     uint32_t env = b->env_id[e];
-    int a[20];
+    uint32_t *bel = b->belief + b->agent_off[e];
+    int radio = (flags & OR_RADIO) != 0;
+    int a[20], target[20];
 
-    /* 1 actions */
+    /* 1 actions (and, with OR_RADIO, radio targets; reading R29) */
     for (int i = 0; i < n; ++i) {
         int v = act ? act[i] : -1;
-        if (v == -1)
-            v = (int)or_range(or_draw(seed, env, OR_STREAM_ACTION, (uint32_t)(i >> 2),
-                                      b->steps[e], 0, i & 3), 5u);
-        if (v < 0 || v > 4) v = 0;
-        a[i] = v;
+        target[i] = i;
+        if (v == -1) {
+            a[i] = (int)or_range(or_draw(seed, env, OR_STREAM_ACTION, (uint32_t)(i >> 2),
+                                         b->steps[e], 0, i & 3), 5u);
+            if (radio)
+                target[i] = (int)or_range(or_draw(seed, env, OR_STREAM_RADIO, (uint32_t)(i >> 2),
+                                                  b->steps[e], 0, i & 3), (uint32_t)n);
+        } else if (radio && v >= 0) {
+            /* move v mod 5; v div 5 = 0 no message, 1..n agent (v div 5) - 1 */
+            a[i] = v % 5;
+            if (v / 5 >= 1 && v / 5 <= n) target[i] = v / 5 - 1;
+        } else {
+            a[i] = (v >= 0 && v <= 4) ? v : 0;
+        }
     }
 
     /* 2 moves */
@@ -508,6 +539,7 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
                 count[i] += 1;
                 count[h] += 1;
                 b->found[e] |= 1u << h;
+                if (radio) bel[i] |= 1u << h; /* a seeker knows the hiders it sees */
             }
         }
     }
@@ -550,6 +582,19 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
             rew[i] = (float)v;
     }
 
+    /* 3c radio (reading R29, OR_RADIO): every agent whose target is another
+     * agent sends it its belief as it stands after this step's sightings;
+     * all messages of a step are delivered together (a message received now
+     * is forwarded from the next step on). Tiles are not sent: the seekers'
+     * discovery map already pools every seeker's visible cells and hiders
+     * keep no map. */
+    if (radio) {
+        uint32_t sent[20];
+        for (int i = 0; i < n; ++i) sent[i] = bel[i];
+        for (int i = 0; i < n; ++i)
+            if (target[i] != i) bel[target[i]] |= sent[i];
+    }
+
     /* 4 termination / truncation */
     b->t[e] += 1;
     uint32_t hider_mask = 0;
@@ -566,6 +611,7 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
         b->t[e] = 0;
         b->found[e] = 0;
         b->stuck[e] = 0;
+        for (int i = 0; i < n; ++i) bel[i] = 0;
         if (flags & OR_EXPLORE)
             memset(b->disc + b->disc_off[e], 0, sizeof(uint32_t) * (size_t)(H * or_map_row_words(W)));
         or_spawn(sp, walls, px, py, seed, env, b->ep[e]);
@@ -575,7 +621,7 @@ static void or_step_env(or_batch *b, int e, const int8_t *act, uint32_t *obs, fl
     b->steps[e] += 1;
 
     /* 7 observation */
-    or_observe(sp, walls, px, py, obs);
+    or_observe(sp, walls, px, py, bel, obs);
 }
 
 /* n_steps consecutive steps of every env. actions is NULL (every action

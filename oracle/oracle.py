@@ -7,7 +7,8 @@ generator module (paper_2604_27162_amd.workloads), which holds no step logic.
 
 Layout of every array (same contract as the C-ABI library, written here
 independently):
-  obs  one step: concatenation over envs of [n][C][w] uint32, w = ceil((2r+1)^2/32)
+  obs  one step: concatenation over envs of [n][C*w + radio] uint32,
+       w = ceil((2r+1)^2/32), radio = 1 for envs with flag 64 (belief word)
   rew  one step: concatenation over envs of [n] float32
   done one step: [n_envs] uint8, bit 0 terminated, bit 1 truncated
 """
@@ -75,6 +76,7 @@ class _Batch(ctypes.Structure):
         ("disc_total", ctypes.c_int64),
         ("disc", ctypes.c_void_p),
         ("stuck", ctypes.c_void_p),
+        ("belief", ctypes.c_void_p),
     ]
 
 
@@ -160,7 +162,8 @@ class OracleBatch:
         d = 2 * r.astype(np.int64) + 1
         w = (d * d + 31) // 32
         cells = (H.astype(np.int64) * W)
-        per_obs = n.astype(np.int64) * C * w
+        radio = (self.spec[:, 7] & 64) != 0
+        per_obs = n.astype(np.int64) * (C * w + radio)
         self.n_envs = ne
         self.grid_off = np.zeros(ne, np.int64)
         self.agent_off = np.zeros(ne, np.int64)
@@ -188,6 +191,7 @@ class OracleBatch:
         self.steps = np.zeros(ne, np.uint32)
         self.seed = np.zeros(ne, np.uint64)
         self.stuck = np.zeros(ne, np.uint32)
+        self.belief = np.zeros(max(self.agents_total, 1), np.uint32)
         if env_ids is None:
             self.env_id = (np.arange(ne, dtype=np.uint64) + env_id_base).astype(np.uint32)
         else:
@@ -199,7 +203,7 @@ class OracleBatch:
             self.found.ctypes.data, self.t.ctypes.data, self.ep.ctypes.data,
             self.steps.ctypes.data, self.seed.ctypes.data, self.env_id.ctypes.data,
             self.disc_off.ctypes.data, self.disc_total, self.disc.ctypes.data,
-            self.stuck.ctypes.data)
+            self.stuck.ctypes.data, self.belief.ctypes.data)
 
     def reset(self, seed: int) -> np.ndarray:
         obs0 = np.zeros(self.obs_total, np.uint32)
@@ -234,7 +238,8 @@ class OracleBatch:
         return dict(walls=self.walls.copy(), pos_x=self.px.copy(), pos_y=self.py.copy(),
                     found=self.found.copy(), t=self.t.copy(), episode=self.ep.copy(),
                     steps=self.steps.copy(), seed=self.seed.copy(), env_id=self.env_id.copy(),
-                    discovered=self.disc[:self.disc_total].copy(), stuck=self.stuck.copy())
+                    discovered=self.disc[:self.disc_total].copy(), stuck=self.stuck.copy(),
+                    belief=self.belief[:self.agents_total].copy())
 
     def set_state(self, st: dict) -> None:
         self.walls[:] = st["walls"]
@@ -250,6 +255,8 @@ class OracleBatch:
             self.disc[:self.disc_total] = st["discovered"]
         if "stuck" in st:  # optional: stuck agents of terrain envs
             self.stuck[:] = st["stuck"]
+        if "belief" in st:  # optional: per-agent beliefs of radio envs
+            self.belief[:self.agents_total] = st["belief"]
 
 
 def spawn(spec: dict, walls: np.ndarray, seed: int, env: int, episode: int):

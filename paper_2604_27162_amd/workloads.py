@@ -31,6 +31,7 @@ DESYNC = 4
 OCCLUDE = 8  # line-of-sight occlusion in the windows
 EXPLORE = 16  # exploration rewards and per-env discovery maps
 TERRAIN = 32  # tile types, agent classes, move chances, stuck and rescue
+RADIO = 64  # per-agent hider beliefs shared by radio messages
 WALKER, SWIMMER, FLYER = 0, 1, 2
 DEFAULT_FLAGS = COLLIDE | CAPTURE_ENDS | DESYNC
 EPISODE_LEN = 256
@@ -78,6 +79,8 @@ WORKLOADS = {
     "uneven8k": dict(n_envs=8192, spec=None, steps=2000, seed=4, spec_seed=4),
     "terrain4k": dict(n_envs=4096, spec=with_terrain(spec(32, 32, 10, 4, 4, 10)), steps=2000,
                       seed=5),
+    "radio4k": dict(n_envs=4096, spec=spec(32, 32, 10, 4, 4, 10, flags=DEFAULT_FLAGS | RADIO),
+                    steps=2000, seed=6),
 }
 
 
@@ -116,6 +119,27 @@ def random_actions(n_steps: int, agents_total: int, seed: int, draw_frac: float 
         bad = g.random(a.shape) < invalid_frac
         a[bad] = g.choice(np.array([5, 7, 100, -2, -128], np.int8), size=int(bad.sum()))
     return a
+
+
+def radio_actions(n_steps: int, specs, seed: int, draw_frac: float = 0.0,
+                  msg_frac: float = 0.5) -> np.ndarray:
+    """External int8 actions [n_steps][agents_total] for radio envs: move m
+    in 0..4 plus 5 * (target + 1) for a fraction of agents (target uniform
+    over the env's agents, itself included), some codes past the last agent
+    (no message), and a fraction of -1 (move and target drawn)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    cols = []
+    for s in specs:
+        n = int(s["n"])
+        m = g.integers(0, 5, size=(n_steps, n))
+        code = np.where(g.random((n_steps, n)) < msg_frac, g.integers(1, n + 1, size=(n_steps, n)), 0)
+        over = g.random((n_steps, n)) < 0.03
+        code = np.where(over, g.integers(n + 1, 25, size=(n_steps, n)), code)
+        cols.append(m + 5 * code)
+    a = np.concatenate(cols, axis=1).astype(np.int16)
+    if draw_frac > 0:
+        a[g.random(a.shape) < draw_frac] = -1
+    return a.astype(np.int8)
 
 
 def serving_trace(n_requests: int = 64, rate_per_s: float = 100.0, seed: int = 5) -> list:

@@ -12,6 +12,7 @@ from oracle import oracle as o
 from tests import bruteforce_spec as bf
 from tests import test_oracle_explore as explore
 from tests import test_oracle_golden as golden
+from tests import test_oracle_radio as radio
 from tests import test_oracle_rng as rng
 from tests import test_oracle_terrain as terrain
 
@@ -89,6 +90,20 @@ MUTATIONS = {
     "terrain_stuck_kept_at_auto_reset": (
         "        b->found[e] = 0;\n        b->stuck[e] = 0;\n        if (flags & OR_EXPLORE)",
         "        b->found[e] = 0;\n        if (flags & OR_EXPLORE)"),
+    "radio_sequential_delivery": ("if (target[i] != i) bel[target[i]] |= sent[i];",
+                                  "if (target[i] != i) bel[target[i]] |= bel[i];"),
+    "radio_message_overwrites": ("if (target[i] != i) bel[target[i]] |= sent[i];",
+                                 "if (target[i] != i) bel[target[i]] = sent[i];"),
+    "radio_target_off_by_one": ("if (v / 5 >= 1 && v / 5 <= n) target[i] = v / 5 - 1;",
+                                "if (v / 5 >= 1 && v / 5 < n) target[i] = v / 5;"),
+    "radio_move_ignored_with_target": ("a[i] = v % 5;", "a[i] = v <= 4 ? v : 0;"),
+    "radio_draw_misses_last_agent": ("b->steps[e], 0, i & 3), (uint32_t)n);",
+                                     "b->steps[e], 0, i & 3), (uint32_t)n - 1u);"),
+    "radio_draw_stream": ("OR_STREAM_RADIO, (uint32_t)(i >> 2)", "OR_STREAM_ACTION, (uint32_t)(i >> 2)"),
+    "radio_sight_not_recorded": ("if (radio) bel[i] |= 1u << h;", "if (0) bel[i] |= 1u << h;"),
+    "radio_beliefs_kept_at_reset": ("        for (int i = 0; i < n; ++i) bel[i] = 0;\n",
+                                    "        for (int i = 0; i < n && 0; ++i) bel[i] = 0;\n"),
+    "radio_belief_word_missing": ("oi[aw - 1] = belief[i];", "oi[aw - 1] = 0;"),
 }
 
 
@@ -149,7 +164,12 @@ def run_pins(libpath, rocrand_philox):
             ("terrain_generation", lambda: terrain.check_generation(rocrand_philox, libpath)),
             ("terrain_chances", lambda: terrain.check_chances(libpath)),
             ("terrain_invariants",
-             lambda: terrain.check_trajectory_invariants(libpath, n_envs=40, steps=100))]
+             lambda: terrain.check_trajectory_invariants(libpath, n_envs=40, steps=100)),
+            ("radio_golden", lambda: radio.check_hand_worked(libpath)),
+            ("radio_plain", lambda: radio.check_reduces_to_plain(libpath, n_envs=12, steps=60)),
+            ("radio_draws", lambda: radio.check_radio_draws(rocrand_philox, libpath)),
+            ("radio_invariants",
+             lambda: radio.check_trajectory_invariants(libpath, n_envs=20, steps=60))]
     for name, fn in pins:
         try:
             fn()

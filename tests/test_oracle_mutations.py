@@ -38,7 +38,7 @@ MUTATIONS = {
                             "or_spawn(sp, walls, px, py, seed, env, b->ep[e] - 1);"),
     "action_keyed_by_t": ("b->steps[e], 0, i & 3), 5u);", "b->t[e], 0, i & 3), 5u);"),
     "obs_before_reset": ("    /* 5 auto-reset (the new episode's discovery map is empty) */\n    if (d) {",
-                         "    or_observe(sp, walls, px, py, obs);\n    if (0) {"),
+                         "    or_observe(sp, walls, px, py, bel, obs);\n    if (0) {"),
     "opponent_as_teammate": ("if (or_is_seeker(j, S) == or_is_seeker(i, S))", "if (1)"),
     "los_corner_touch_blocks": ("return a.num * b.den < b.num * a.den;",
                                 "return a.num * b.den <= b.num * a.den;"),
@@ -52,8 +52,8 @@ MUTATIONS = {
     "explore_counted_after_update": ("if (pass == 0) {", "if (pass == 1) {"),
     "hiders_explore": ("for (int i = 0; i < S && i < n; ++i) {", "for (int i = 0; i < n; ++i) {"),
     "explore_map_kept_at_auto_reset": (
-        "        b->stuck[e] = 0;\n        if (flags & OR_EXPLORE)\n            memset(",
-        "        b->stuck[e] = 0;\n        if (0)\n            memset("),
+        " bel[i] = 0;\n        if (flags & OR_EXPLORE)\n            memset(",
+        " bel[i] = 0;\n        if (0)\n            memset("),
     "explore_ignores_occlusion": (
         "if ((flags & OR_OCCLUDE) && !or_visible(sp, walls, px[i], py[i], cx, cy))\n                            continue;",
         "if (0)\n                            continue;"),
@@ -88,8 +88,8 @@ MUTATIONS = {
         "int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx] == OR_WALL;",
         "int blocking = !or_in_bounds(bx, by, W, H) || walls[by * W + bx] != OR_GROUND;"),
     "terrain_stuck_kept_at_auto_reset": (
-        "        b->found[e] = 0;\n        b->stuck[e] = 0;\n        if (flags & OR_EXPLORE)",
-        "        b->found[e] = 0;\n        if (flags & OR_EXPLORE)"),
+        "        b->found[e] = 0;\n        b->stuck[e] = 0;\n        for (int i = 0;",
+        "        b->found[e] = 0;\n        for (int i = 0;"),
     "radio_sequential_delivery": ("if (target[i] != i) bel[target[i]] |= sent[i];",
                                   "if (target[i] != i) bel[target[i]] |= bel[i];"),
     "radio_message_overwrites": ("if (target[i] != i) bel[target[i]] |= sent[i];",

@@ -80,6 +80,20 @@ extern "C" {
  * the tiles the agent's class may not enter. With HASE_OCCLUDE, only walls
  * and cells outside the map block sight. */
 #define HASE_TERRAIN 32u
+/* radio belief sharing (Sec. 3.3, radio paragraph; the 1-D belief vector of
+ * the observation space, Sec. 3.1): every agent keeps a belief word, bit h
+ * set when it knows of hider h this episode (empty at every episode start).
+ * After the detections of a step a seeker's belief gains the hiders it sees;
+ * then every agent whose radio target is another agent sends it its belief,
+ * all messages formed before any is delivered, and the receiver ORs it in
+ * (so the beliefs of an env together equal its found word). Targets come
+ * with the actions: a drawn action also draws a target (the RADIO stream,
+ * uniform over the n agents, the agent itself meaning no message); an
+ * external action v >= 0 moves v mod 5 and names target v / 5 - 1 (v / 5 = 0
+ * or > n: no message); other negative values than -1 stay without a message.
+ * Each agent's observation ends with its belief word after the channels.
+ * Radio changes no move, reward or episode end. */
+#define HASE_RADIO 64u
 
 /* step modes */
 #define HASE_STEP_PERSISTENT 0u  /* all n_steps in one launch per tile variant (graph-replayed) */
@@ -97,7 +111,7 @@ extern "C" {
  *   wall_pct       0..99: each cell is an iid blocking tile with this
  *                  probability (integer threshold, see hase_reset)
  *   flags          HASE_COLLIDE | HASE_CAPTURE_ENDS | HASE_DESYNC |
- *                  HASE_OCCLUDE | HASE_EXPLORE | HASE_TERRAIN
+ *                  HASE_OCCLUDE | HASE_EXPLORE | HASE_TERRAIN | HASE_RADIO
  *   episode_len    L in 1..65535: truncation when t reaches L
  * Terrain fields (read only with HASE_TERRAIN; 0 otherwise):
  *   water_pct, mud_pct  percent of water and mud cells, wall_pct + water_pct
@@ -138,10 +152,12 @@ typedef struct hase_batch_desc {
 
 /*
  * Sizes of a batch. Per step the outputs are
- *   obs   obs_words_per_step uint32: env e's [n][C][w] block (w =
- *         ceil((2r+1)^2 / 32)) starts at word obs_off[e] (hase_get_offsets);
- *         for agent i, channel c the window bit k = (dy+r)(2r+1) + (dx+r) is
- *         bit (k & 31) of word (i*C + c)*w + (k >> 5); unused bits are 0.
+ *   obs   obs_words_per_step uint32: env e's [n][C*w + b] block (w =
+ *         ceil((2r+1)^2 / 32), b = 1 for HASE_RADIO envs, else 0) starts at
+ *         word obs_off[e] (hase_get_offsets); for agent i, channel c the
+ *         window bit k = (dy+r)(2r+1) + (dx+r) is bit (k & 31) of word
+ *         i*(C*w + b) + c*w + (k >> 5); unused bits are 0; a radio env's
+ *         agent i has its belief word at i*(C*w + 1) + C*w.
  *         Channels: 0 blocking tile or outside the map, 1 another agent of the
  *         same role, 2 an agent of the other role, 3 outside the map.
  *   rew   agents_total float32: env e's agents start at agent_off[e]
@@ -182,6 +198,10 @@ typedef struct hase_layout {
  *            (the map layout above); may be NULL: get_state then skips the
  *            maps and set_state clears every map; set_state rejects a map
  *            with bits past the width (HASE_ESTATE)
+ *   belief   [agents_total] radio beliefs (HASE_RADIO envs: bit h = hider h
+ *            known; other envs 0); may be NULL: get_state skips it and
+ *            set_state clears it; set_state rejects bits that are not hiders
+ *            of a radio env (HASE_ESTATE)
  * Env ids are not part of the state: they come from the batch descriptor.
  */
 typedef struct hase_host_state {
@@ -191,6 +211,7 @@ typedef struct hase_host_state {
     uint64_t *seed;
     uint32_t *discovered;
     uint32_t *stuck;
+    uint32_t *belief;
 } hase_host_state;
 
 typedef struct hase_batch hase_batch;
@@ -220,7 +241,8 @@ int hase_get_map_offsets(const hase_batch *b, uint64_t *h_map_off);
  * walls (terrain: tile types) from the generator, free-cell check (HASE_EGRID
  * names the first env with fewer free cells than agents, or with terrain,
  * fewer than n cells some agent's class may stand on), agents spawned,
- * counters, stuck agents and discovery maps cleared, desync offset drawn;
+ * counters, stuck agents, discovery maps and beliefs cleared, desync offset
+ * drawn;
  * writes the first observation to d_obs0
  * (obs_words_per_step words; may be NULL). Synchronises the stream.
  */
@@ -233,6 +255,7 @@ int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0);
  *   d_actions  NULL (every action drawn from the generator) or
  *              [n_steps][agents_total] int8; -1 = draw, 0 stay, 1 N (y-1),
  *              2 S (y+1), 3 E (x+1), 4 W (x-1), anything else = stay
+ *              (HASE_RADIO envs: move and radio target packed, see there)
  *   d_obs      [n_steps][obs_words_per_step] uint32
  *   d_rew      [n_steps][agents_total] float32
  *   d_done     [n_steps][n_envs] uint8

@@ -67,7 +67,7 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 }
 
 // Counter layout: (env id, stream << 24 | sub, a, b).
-enum : uint32_t { ST_ACTION = 0u, ST_SPAWN = 1u, ST_WALL = 2u, ST_DESYNC = 3u, ST_MOVE = 4u };
+enum : uint32_t { ST_ACTION = 0u, ST_SPAWN = 1u, ST_WALL = 2u, ST_DESYNC = 3u, ST_MOVE = 4u, ST_RADIO = 5u };
 
 // floor(x * m / 2^32)
 __device__ __forceinline__ uint32_t range_map(uint32_t x, uint32_t m) { return __umulhi(x, m); }
@@ -860,6 +860,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     constexpr bool FEAT_OK = KIND != KIND_PLAIN;
     constexpr bool XPL = (KIND & KIND_EXPLORE) != 0;  // every env of the tile explores
     constexpr bool TER = (KIND & KIND_TERRAIN) != 0;  // every env of the tile has terrain
+    constexpr bool RAD = (KIND & KIND_RADIO) != 0;    // every env of the tile has radio
 
     const uint32_t obs_off = gp(J.tab.obs_off)[e], agent_off = gp(J.tab.agent_off)[e];
     const uint32_t env = gp(J.tab.env_id)[e];
@@ -971,6 +972,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         hbit[m] = (a < n && a >= S) ? 1u << a : 0u;
         rsign[m] = a < S ? 1 : -1;
     }
+    // radio: each task's belief (bit h: the agent knows of hider h)
+    uint32_t bel[TPL];
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+        const int a = l + m * LANES;
+        bel[m] = (RAD && a < n) ? gp(J.bel)[agent_off + (uint32_t)a] : 0u;
+    }
     // termination needs every hider found; without capture-ends (or without
     // hiders) the test uses bit 31, which no agent sets
     const uint32_t tmask = ((flags & 2u) && n > S) ? hmask : 0x80000000u;
@@ -1020,7 +1028,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         GAS float *rew_l[TPL];
 #pragma unroll
         for (int m = 0; m < TPL; ++m) {
-            obs_l[m] = obs_p + (uint32_t)((l + m * LANES) * C * W);
+            obs_l[m] = obs_p + (uint32_t)((l + m * LANES) * (C * W + (RAD ? 1 : 0)));
             rew_l[m] = obs_only ? nullptr : rew_p + (uint32_t)(l + m * LANES);
         }
         auto store_obs = [&](int m) __attribute__((always_inline)) {
@@ -1029,6 +1037,8 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             store_words<W>(oa + W, team[m]);
             store_words<W>(oa + 2 * W, opp[m]);
             if (want_out) store_words<W>(oa + 3 * W, outm[m]);
+            // radio: the belief word follows the channels
+            if constexpr (RAD) oa[want_out ? 4 * W : 3 * W] = bel[m];
         };
 
         if (obs_only) {
@@ -1044,7 +1054,30 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         // One step from the generator's actions of this step (3 bits per
         // agent); all of its stores are issued together at the end.
         auto step = [&](uint64_t acts) __attribute__((always_inline)) {
-            // ---- 1 external actions override the drawn ones (-1 keeps the draw)
+            // ---- 1 radio targets of this lane's tasks (own index: no
+            // message): the RADIO draw, word a & 3 of block a >> 2, mapped
+            // to 0..n-1, unless an external action names one
+            uint32_t tgt_r[TPL];
+            if constexpr (RAD) {
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const uint32_t a = (uint32_t)(l + m * LANES);
+                    const U4 x = philox(env, (ST_RADIO << 24) | (a >> 2), steps, 0u, k0, k1);
+                    const uint32_t w = pick((a & 2u) != 0u, pick((a & 1u) != 0u, x.w, x.z),
+                                            pick((a & 1u) != 0u, x.y, x.x));
+                    tgt_r[m] = range_map(w, (uint32_t)n);
+                    if (has_act && (int)a < n) {
+                        const int v = act_p[a];
+                        if (v != -1) {
+                            // v >= 0: target v div 5 - 1 (0 or past the last agent: none)
+                            const uint32_t c = v >= 0 ? (uint32_t)v / 5u : 0u;
+                            tgt_r[m] = (c >= 1u && c <= (uint32_t)n) ? c - 1u : a;
+                        }
+                    }
+                }
+            }
+            // ---- 1 external actions override the drawn ones (-1 keeps the
+            // draw); with radio a value v >= 0 moves v mod 5
             if (has_act) {
                 uint64_t ov = 0, om = 0;
 #pragma unroll
@@ -1052,7 +1085,8 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     if (i < n) {
                         const int v = act_p[i];
                         if (v != -1) {
-                            const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                            uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                            if constexpr (RAD) a = v >= 0 ? (uint32_t)v % 5u : 0u;
                             ov |= (uint64_t)a << (3 * i);
                             om |= 7ull << (3 * i);
                         }
@@ -1260,6 +1294,47 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 found |= group_or_dpp<LANES>(seen_h);
             }
 
+            // ---- 3c radio: a seeker's belief gains the hiders it sees (an
+            // opponent bit at the hider's window cell: in the window and, with
+            // line of sight, visible); then every agent sends its belief to
+            // its target, all messages formed before any is delivered
+            if constexpr (RAD) {
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    uint32_t sh = 0u;
+#pragma unroll
+                    for (int h = 0; h < NMAX; ++h) {
+                        const uint32_t u = (uint32_t)(pp[h] - mine[m]) + (uint32_t)(R * 256 + R);
+                        const uint32_t lo = u & 0xffu, hi = u >> 8;
+                        const bool in = (lo > hi ? lo : hi) < (uint32_t)D;
+                        const uint32_t k = in ? hi * (uint32_t)D + lo : 0u;
+                        uint32_t wv = opp[m][0];
+#pragma unroll
+                        for (int wi = 1; wi < W; ++wi) wv = pick((k >> 5) == (uint32_t)wi, opp[m][wi], wv);
+                        const bool hit = in && h >= S && h < n && ((wv >> (k & 31u)) & 1u) != 0u;
+                        sh |= hit ? 1u << h : 0u;
+                    }
+                    bel[m] |= seeker[m] ? sh : 0u;
+                }
+                uint32_t inc[TPL];
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) inc[m] = 0u;
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    // agent i is task i / LANES of lane i % LANES of the env
+                    uint32_t pk = bel[i / LANES] | (tgt_r[i / LANES] << 27);
+                    if constexpr (LANES > 1) pk = (uint32_t)__shfl((int)pk, q * LANES + i % LANES, 64);
+                    const uint32_t ti = pk >> 27, bi = pk & 0x07ffffffu;
+#pragma unroll
+                    for (int m = 0; m < TPL; ++m) {
+                        const uint32_t a = (uint32_t)(l + m * LANES);
+                        inc[m] |= (i < n && ti == a && (uint32_t)i != a) ? bi : 0u;
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) bel[m] |= inc[m];
+            }
+
             // ---- 4 termination / truncation
             t += 1u;
             const uint32_t d = ((found & tmask) == tmask ? 1u : 0u) | (t >= Lep ? 2u : 0u);
@@ -1287,6 +1362,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 ep += 1u;
                 t = 0u;
                 found = 0u;
+                // and with empty beliefs
+                if constexpr (RAD) {
+#pragma unroll
+                    for (int m = 0; m < TPL; ++m) bel[m] = 0u;
+                }
                 // the new episode starts with an empty discovery map
                 if constexpr (XP)
                     for (uint32_t i = (uint32_t)l; i < map_words; i += LANES) mslot[i] = 0u;
@@ -1454,6 +1534,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         }
         if constexpr (TER) {
             if (l == 0) gp(J.stuck)[e] = stuck;
+        }
+        if constexpr (RAD) {
+#pragma unroll
+            for (int m = 0; m < TPL; ++m)
+                if (mine_live[m]) gp(J.bel)[agent_off + (uint32_t)(l + m * LANES)] = bel[m];
         }
     }
 }

@@ -77,6 +77,7 @@ struct JobDesc {
     uint32_t *stuck;      // stuck agents per env (terrain)
     uint32_t *map;        // per-step map output, may be null
     uint64_t map_stride;  // map words per output step
+    uint32_t *bel;        // per-agent hider beliefs (radio), at tab.agent_off[e]
 };
 
 // A wave's work: envs perm[env0 .. env0 + count) of job `job` (count <= 64 /
@@ -95,6 +96,7 @@ struct InitArgs {
     uint32_t *bb;
     uint32_t *disc;       // discovery maps, cleared at reset
     uint32_t *stuck;      // stuck agents, cleared at reset
+    uint32_t *bel;        // per-agent beliefs, cleared at reset
     uint32_t *err;        // min over envs with too few free cells (reset only)
     uint64_t seed_value;
     uint32_t n_envs;
@@ -108,11 +110,12 @@ constexpr int KIND_PLAIN = 0;    // no line of sight, no exploration, no terrain
 constexpr int KIND_EXPLORE = 1;  // bit 0: exploration
 constexpr int KIND_LOS = 2;      // bit 1: line of sight
 constexpr int KIND_TERRAIN = 4;  // bit 2: terrain
-constexpr int N_KINDS = 8;       // kinds 0..7
+constexpr int KIND_RADIO = 8;    // bit 3: radio belief sharing
+constexpr int N_KINDS = 16;      // kinds 0..15
 inline int env_kind(uint32_t flags)
 {
     return ((flags & 8u) ? KIND_LOS : 0) | ((flags & 16u) ? KIND_EXPLORE : 0) |
-           ((flags & 32u) ? KIND_TERRAIN : 0);
+           ((flags & 32u) ? KIND_TERRAIN : 0) | ((flags & 64u) ? KIND_RADIO : 0);
 }
 
 // Launch the step kernel for tile range [tile0, tile0 + n_tiles) of variant
@@ -136,7 +139,9 @@ hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 // Per-lanes entry points, one translation unit each: single-variant and
 // mixed plain kernels (hase_step_l<L>.hip, hase_mixed_l<L>.hip), the line of
 // sight and exploration kinds (hase_feat_l<L>.hip) and the terrain kinds
-// (hase_terr_l<L>.hip, with line of sight hase_terrlos_l<L>.hip).
+// (hase_terr_l<L>.hip, with line of sight hase_terrlos_l<L>.hip); the radio
+// kinds without terrain (hase_radio_l<L>.hip) and with it
+// (hase_radioter_l<L>.hip).
 #define HASE_DECLARE_LANES(L)                                                                     \
     hipError_t launch_step_lanes##L(int nmax, int r, const Tile *tiles, uint32_t n_tiles,        \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
@@ -156,7 +161,15 @@ hipError_t launch_init(const InitArgs &a, hipStream_t stream);
     hipError_t launch_terrlos_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,            \
                                        const JobDesc *jobs, const JobDesc &job0, uint32_t K,      \
                                        uint32_t step_base, uint32_t slot_words,                   \
-                                       uint32_t map_words, hipStream_t stream);
+                                       uint32_t map_words, hipStream_t stream);                   \
+    hipError_t launch_radio_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,              \
+                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,        \
+                                     uint32_t step_base, uint32_t slot_words, uint32_t map_words, \
+                                     hipStream_t stream);                                         \
+    hipError_t launch_radioter_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,           \
+                                        const JobDesc *jobs, const JobDesc &job0, uint32_t K,     \
+                                        uint32_t step_base, uint32_t slot_words,                  \
+                                        uint32_t map_words, hipStream_t stream);
 HASE_DECLARE_LANES(1)
 HASE_DECLARE_LANES(2)
 HASE_DECLARE_LANES(4)

@@ -10,7 +10,8 @@ namespace hase {
 
 // One 64-lane block per env: walls (terrain: tile types) from the generator
 // (reset) or loaded (rebuild), padded board planes, free-cell check, spawn of
-// episode 0, desync, empty discovery map (exploring envs), nobody stuck.
+// episode 0, desync, empty discovery map (exploring envs), nobody stuck, no
+// beliefs.
 __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
 {
     __shared__ uint8_t cellw[MAX_SIDE * MAX_SIDE];
@@ -133,6 +134,7 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
         A.ep[e] = 0;
         A.steps[e] = 0;
         A.stuck[e] = 0;
+        for (int j = 0; j < n; ++j) A.bel[ao + (uint32_t)j] = 0u;
         uint32_t t0 = 0;
         if (flags & 4u) t0 = range_map(philox(env, ST_DESYNC << 24, 0u, 0u, k0, k1).x, Lep);
         A.t[e] = t0;
@@ -175,6 +177,13 @@ hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles
         if (kind == KIND_PLAIN)                                                                     \
             return launch_mixed_lanes##L(tiles, n_tiles, jobs, job0, K, step_base, slot_words,      \
                                          map_words, stream);                                        \
+        if (kind & KIND_RADIO) {                                                                    \
+            if (kind & KIND_TERRAIN)                                                                \
+                return launch_radioter_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base,     \
+                                                slot_words, map_words, stream);                     \
+            return launch_radio_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base,            \
+                                         slot_words, map_words, stream);                            \
+        }                                                                                           \
         if (kind & KIND_TERRAIN)                                                                    \
             return launch_terr_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base, slot_words, \
                                         map_words, stream);                                         \

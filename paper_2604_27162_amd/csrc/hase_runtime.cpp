@@ -104,7 +104,7 @@ int check_spec(const hase_env_spec &s, uint32_t idx)
     if (s.n_channels != 3 && s.n_channels != 4)
         return fail(HASE_EINVAL, "spec %u: n_channels must be 3 or 4", idx);
     if (s.wall_pct > 99) return fail(HASE_EINVAL, "spec %u: wall_pct must be <= 99", idx);
-    if (s.flags & ~63u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
+    if (s.flags & ~127u) return fail(HASE_EINVAL, "spec %u: unknown flag bits", idx);
     if (s.episode_len < 1) return fail(HASE_EINVAL, "spec %u: episode_len must be >= 1", idx);
     if (s.flags & HASE_TERRAIN) {
         if ((int)s.wall_pct + s.water_pct + s.mud_pct > 99)
@@ -123,7 +123,7 @@ int check_spec(const hase_env_spec &s, uint32_t idx)
 
 struct Regions {
     size_t perm, spec0, spec1, spec2, obs_off, agent_off, bb_off, grid_off, env_id, map_off, terr;
-    size_t seed, found, t, ep, steps, stuck, pos, walls, bb, disc, tiles, err, total;
+    size_t seed, found, t, ep, steps, stuck, bel, pos, walls, bb, disc, tiles, err, total;
 };
 
 struct Plan {
@@ -163,7 +163,9 @@ int make_plan(const hase_batch_desc *d, Plan &p)
         p.grid_off[e] = (uint32_t)p.cells;
         p.bb_off[e] = (uint32_t)p.bb_words;
         p.map_off[e] = (uint32_t)p.map_words;
-        p.obs_words += (uint64_t)s.n_agents * s.n_channels * words_per_channel(s.view_radius);
+        // radio envs: one belief word after each agent's channels
+        p.obs_words += (uint64_t)s.n_agents *
+                       (s.n_channels * words_per_channel(s.view_radius) + ((s.flags & HASE_RADIO) ? 1 : 0));
         p.agents += s.n_agents;
         p.cells += (uint64_t)s.height * s.width;
         // terrain envs keep two board planes (tile types)
@@ -199,6 +201,7 @@ int make_plan(const hase_batch_desc *d, Plan &p)
     r.ep = take(4ull * N);
     r.steps = take(4ull * N);
     r.stuck = take(4ull * N);
+    r.bel = take(4ull * p.agents);
     r.pos = take(2ull * p.agents);
     r.walls = take(p.cells);
     r.bb = take(4ull * p.bb_words);
@@ -381,6 +384,7 @@ JobDesc make_job(const hase_batch *b, const int8_t *act, uint32_t *obs, float *r
     j.out_step0 = 0;
     j.disc = b->at<uint32_t>(r.disc);
     j.stuck = b->at<uint32_t>(r.stuck);
+    j.bel = b->at<uint32_t>(r.bel);
     j.map = map;
     j.map_stride = b->plan.map_words;
     return j;
@@ -504,6 +508,7 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
     a.bb = b->at<uint32_t>(r.bb);
     a.disc = b->at<uint32_t>(r.disc);
     a.stuck = b->at<uint32_t>(r.stuck);
+    a.bel = b->at<uint32_t>(r.bel);
     a.err = b->at<uint32_t>(r.err);
     a.seed_value = seed;
     a.n_envs = b->n_envs;
@@ -514,7 +519,7 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
 // Mutable per-env state (walls and bitboards never change while stepping).
 struct Snapshot {
     std::vector<uint16_t> pos;
-    std::vector<uint32_t> found, t, ep, steps, stuck, disc;
+    std::vector<uint32_t> found, t, ep, steps, stuck, disc, bel;
 };
 
 int snapshot_take(hase_batch *b, Snapshot &s)
@@ -528,6 +533,7 @@ int snapshot_take(hase_batch *b, Snapshot &s)
     s.steps.resize(N);
     s.stuck.resize(N);
     s.disc.resize(p.map_words);
+    s.bel.resize(p.agents);
     auto down = [&](void *dst, size_t off, size_t bytes) {
         return hipMemcpyAsync(dst, b->d + off, bytes, hipMemcpyDeviceToHost, b->stream);
     };
@@ -537,6 +543,7 @@ int snapshot_take(hase_batch *b, Snapshot &s)
     HIP_TRY(down(s.ep.data(), p.reg.ep, 4ull * N));
     HIP_TRY(down(s.steps.data(), p.reg.steps, 4ull * N));
     HIP_TRY(down(s.stuck.data(), p.reg.stuck, 4ull * N));
+    HIP_TRY(down(s.bel.data(), p.reg.bel, 4ull * p.agents));
     if (p.map_words) HIP_TRY(down(s.disc.data(), p.reg.disc, 4ull * p.map_words));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return HASE_OK;
@@ -555,6 +562,7 @@ int snapshot_restore(hase_batch *b, const Snapshot &s)
     HIP_TRY(up(p.reg.ep, s.ep.data(), 4ull * N));
     HIP_TRY(up(p.reg.steps, s.steps.data(), 4ull * N));
     HIP_TRY(up(p.reg.stuck, s.stuck.data(), 4ull * N));
+    HIP_TRY(up(p.reg.bel, s.bel.data(), 4ull * p.agents));
     if (p.map_words) HIP_TRY(up(p.reg.disc, s.disc.data(), 4ull * p.map_words));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return HASE_OK;
@@ -794,6 +802,7 @@ int hase_get_state(hase_batch *b, const hase_host_state *out)
     if (out->discovered && p.map_words)
         HIP_TRY(down(out->discovered, p.reg.disc, 4ull * p.map_words));
     if (out->stuck) HIP_TRY(down(out->stuck, p.reg.stuck, 4ull * N));
+    if (out->belief) HIP_TRY(down(out->belief, p.reg.bel, 4ull * p.agents));
     HIP_TRY(hipStreamSynchronize(b->stream));
     for (uint64_t i = 0; i < p.agents; ++i) {
         out->pos_x[i] = (uint8_t)(pos[i] & 0xff);
@@ -828,6 +837,16 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
         if (in->stuck && in->stuck[e] != 0u &&
             (!(s.flags & HASE_TERRAIN) || (in->stuck[e] >> s.n_agents) != 0u))
             return fail(HASE_ESTATE, "env %u: stuck bits of absent agents or without terrain", e);
+        if (in->belief) {
+            // beliefs hold hider bits only, and only in radio envs
+            const uint32_t hm = (s.flags & HASE_RADIO)
+                                    ? (uint32_t)(((1ull << s.n_agents) - 1ull) & ~((1ull << s.n_seekers) - 1ull))
+                                    : 0u;
+            for (uint32_t j = 0; j < s.n_agents; ++j)
+                if (in->belief[p.agent_off[e] + j] & ~hm)
+                    return fail(HASE_ESTATE, "env %u agent %u: belief bits that are not hiders of a radio env",
+                                e, j);
+        }
         if (in->discovered && (s.flags & HASE_EXPLORE)) {
             // map bits past the width are not cells
             const uint32_t rw = (s.width + 31) / 32, tail = s.width & 31u;
@@ -858,6 +877,10 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
         HIP_TRY(up(p.reg.stuck, in->stuck, 4ull * N));
     else
         HIP_TRY(hipMemsetAsync(b->d + p.reg.stuck, 0, 4ull * N, b->stream));
+    if (in->belief)
+        HIP_TRY(up(p.reg.bel, in->belief, 4ull * p.agents));
+    else
+        HIP_TRY(hipMemsetAsync(b->d + p.reg.bel, 0, 4ull * p.agents, b->stream));
     HIP_TRY(launch_init(make_init(b, 0, 1), b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->ready = true;

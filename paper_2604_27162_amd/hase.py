@@ -20,7 +20,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhase.so")
 
 OK, EINVAL, ENOMEM, EGRID, EHIP, ESTATE, ENOTREADY = 0, -1, -2, -3, -4, -5, -6
-COLLIDE, CAPTURE_ENDS, DESYNC, OCCLUDE, EXPLORE, TERRAIN = 1, 2, 4, 8, 16, 32
+COLLIDE, CAPTURE_ENDS, DESYNC, OCCLUDE, EXPLORE, TERRAIN, RADIO = 1, 2, 4, 8, 16, 32, 64
 PERSISTENT, PER_LAUNCH = 0, 1
 N_BUCKETS = 4
 
@@ -57,7 +57,7 @@ class HostState(ctypes.Structure):
                 ("pos_y", ctypes.c_void_p), ("found", ctypes.c_void_p), ("t", ctypes.c_void_p),
                 ("episode", ctypes.c_void_p), ("steps", ctypes.c_void_p),
                 ("seed", ctypes.c_void_p), ("discovered", ctypes.c_void_p),
-                ("stuck", ctypes.c_void_p)]
+                ("stuck", ctypes.c_void_p), ("belief", ctypes.c_void_p)]
 
 
 class StepIO(ctypes.Structure):
@@ -254,11 +254,12 @@ class HaseBatch:
                   t=np.zeros(self.n_envs, np.uint32), episode=np.zeros(self.n_envs, np.uint32),
                   steps=np.zeros(self.n_envs, np.uint32), seed=np.zeros(self.n_envs, np.uint64),
                   discovered=np.zeros(self.map_words, np.uint32),
-                  stuck=np.zeros(self.n_envs, np.uint32))
+                  stuck=np.zeros(self.n_envs, np.uint32),
+                  belief=np.zeros(self.agents, np.uint32))
         hs = HostState(*[st[k].ctypes.data for k in
                          ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")],
                        st["discovered"].ctypes.data if self.map_words else None,
-                       st["stuck"].ctypes.data)
+                       st["stuck"].ctypes.data, st["belief"].ctypes.data)
         _check(load().hase_get_state(self._h, ctypes.byref(hs)))
         return st
 
@@ -286,9 +287,15 @@ class HaseBatch:
             if keep["stuck"].size != self.n_envs:
                 raise ValueError("state field stuck must have one entry per env")
             stuck = keep["stuck"].ctypes.data
+        belief = None  # absent: every belief is empty
+        if st.get("belief") is not None:
+            keep["belief"] = np.ascontiguousarray(st["belief"], dtype=np.uint32).reshape(-1)
+            if keep["belief"].size != self.agents:
+                raise ValueError("state field belief must have one entry per agent")
+            belief = keep["belief"].ctypes.data
         hs = HostState(*[keep[k].ctypes.data for k in
                          ("walls", "pos_x", "pos_y", "found", "t", "episode", "steps", "seed")],
-                       disc, stuck)
+                       disc, stuck, belief)
         _check(load().hase_set_state(self._h, ctypes.byref(hs)))
 
     def offsets(self):

@@ -54,7 +54,7 @@ def test_uniform_layout(lib):
 
 @pytest.mark.parametrize("bad", [dict(H=1), dict(W=65), dict(n=0), dict(n=21), dict(S=5, n=4),
                                  dict(r=0), dict(r=5), dict(C=2), dict(C=5), dict(wall_pct=100),
-                                 dict(flags=64), dict(L=0),
+                                 dict(flags=128), dict(L=0),
                                  dict(flags=32, water_pct=60, mud_pct=40),
                                  dict(flags=32, stuck_pct=101), dict(flags=32, speed=(101,) * 9),
                                  dict(flags=32, classes=3), dict(flags=32, classes=1 << 8)])

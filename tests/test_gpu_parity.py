@@ -231,8 +231,7 @@ def sampled_check(specs, seed, steps, g_out, sample, env_id_base=0):
     go, gr, gd = g_out
     for e in sample:
         s = specs[e]
-        d = 2 * s["r"] + 1
-        nw = s["n"] * s["C"] * ((d * d + 31) // 32)
+        nw = obs_words(s)
         one = o.OracleBatch([s], env_ids=[env_id_base + e])
         one.reset(seed)
         oo, orr, od = one.step(steps)
@@ -243,8 +242,15 @@ def sampled_check(specs, seed, steps, g_out, sample, env_id_base=0):
         np.testing.assert_array_equal(gd[:, e].cpu().numpy(), od[:, 0], err_msg=f"done env {e}")
 
 
+def obs_words(s):
+    """Observation words of one env per step (radio envs: plus one belief
+    word per agent)."""
+    d = 2 * s["r"] + 1
+    return s["n"] * (s["C"] * ((d * d + 31) // 32) + (1 if s["flags"] & wl.RADIO else 0))
+
+
 def offsets(specs):
-    ow = [s["n"] * s["C"] * (((2 * s["r"] + 1) ** 2 + 31) // 32) for s in specs]
+    ow = [obs_words(s) for s in specs]
     na = [s["n"] for s in specs]
     return np.concatenate([[0], np.cumsum(ow)[:-1]]), np.concatenate([[0], np.cumsum(na)[:-1]])
 

@@ -46,6 +46,8 @@ DESCR = {
                  "rescue, 9x9 window, 4 channels",
     "uneven8k": "8192 envs: sides {16,32,64} (50/30/20%), 1..10 agents, 5..25% walls, "
                 "radius 2..4, 4 channels",
+    "radio4k": "4096 envs, 32x32 grid, 10% iid walls, 5 seekers + 5 hiders, 9x9 window, "
+               "4 channels, radio belief sharing (drawn targets, belief word per agent)",
 }
 
 
@@ -56,6 +58,7 @@ def words(r: int) -> int:
 
 EXPLORE = 16
 TERRAIN = 32
+RADIO = 64
 
 
 def map_bytes(s) -> int:
@@ -66,9 +69,9 @@ def map_bytes(s) -> int:
 def out_bytes_per_step(specs, maps: bool = False) -> int:
     """Algorithmic output bytes of one step: packed obs words, one float32
     reward per agent, one uint8 done per env and, with map output, the
-    discovery maps of exploring envs."""
-    return sum(4 * s["n"] * s["C"] * words(s["r"]) + 4 * s["n"] + 1 + (map_bytes(s) if maps else 0)
-               for s in specs)
+    discovery maps of exploring envs; radio envs add a belief word per agent."""
+    return sum(4 * s["n"] * (s["C"] * words(s["r"]) + (1 if s["flags"] & RADIO else 0)) +
+               4 * s["n"] + 1 + (map_bytes(s) if maps else 0) for s in specs)
 
 
 def state_bytes_per_launch(specs) -> int:
@@ -77,7 +80,8 @@ def state_bytes_per_launch(specs) -> int:
     or exploration; write 16 B), agent positions (2 B each way), the padded
     wall bitboard (read; two tile planes with terrain, plus its 24 B of
     classes and chances and the stuck word both ways) and the discovery map
-    of an exploring env (read and write)."""
+    of an exploring env (read and write); radio envs read and write a belief
+    word per agent."""
     tot = 0
     for s in specs:
         P = (s["W"] + 8 + 31) // 32
@@ -86,6 +90,8 @@ def state_bytes_per_launch(specs) -> int:
         if s["flags"] & TERRAIN:
             # second tile plane, terrain words (24 B), stuck word both ways
             feat, board = feat + 24 + 8, 2 * board
+        if s["flags"] & RADIO:
+            feat += 8 * s["n"]
         tot += 56 + feat + 16 + 4 * s["n"] + board + 2 * map_bytes(s)
     return tot
 

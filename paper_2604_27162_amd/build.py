@@ -45,7 +45,14 @@ def build(quiet: bool = False, jobs: int | None = None) -> str:
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     cmds, objs = [], []
-    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+    # the largest translation units (terrain with line of sight or radio)
+    # first, so the longest compiles do not trail the pool
+    def weight(src):
+        name = os.path.basename(src)
+        return (0 if ("radioter" in name or "terrlos" in name) else
+                1 if ("radio" in name or "terr" in name or "feat" in name) else 2, name)
+
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip")), key=weight):
         obj = os.path.join(bdir, os.path.basename(src)[:-4] + ".o")
         cmds.append([_hipcc(), *HIP_FLAGS, "-c", "-o", obj, src])
         objs.append(obj)

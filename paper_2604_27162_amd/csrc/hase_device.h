@@ -1294,28 +1294,35 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 found |= group_or_dpp<LANES>(seen_h);
             }
 
-            // ---- 3c radio: a seeker's belief gains the hiders it sees (an
-            // opponent bit at the hider's window cell: in the window and, with
-            // line of sight, visible); then every agent sends its belief to
-            // its target, all messages formed before any is delivered
+            // ---- 3c radio: a seeker's belief gains the hiders it sees (the
+            // Chebyshev window test; with line of sight the opponent bit at
+            // the hider's window cell, which is already masked by sight);
+            // then every agent sends its belief to its target, all messages
+            // formed before any is delivered
             if constexpr (RAD) {
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) {
                     uint32_t sh = 0u;
 #pragma unroll
                     for (int h = 0; h < NMAX; ++h) {
+                        // absent agents sit at FAR_CELL, outside every window
                         const uint32_t u = (uint32_t)(pp[h] - mine[m]) + (uint32_t)(R * 256 + R);
                         const uint32_t lo = u & 0xffu, hi = u >> 8;
-                        const bool in = (lo > hi ? lo : hi) < (uint32_t)D;
-                        const uint32_t k = in ? hi * (uint32_t)D + lo : 0u;
-                        uint32_t wv = opp[m][0];
+                        bool hit = (lo < (uint32_t)D) & (hi < (uint32_t)D);
+                        if constexpr (LOS) {
+                            const uint32_t k = hit ? hi * (uint32_t)D + lo : 0u;
+                            uint32_t wv = opp[m][0];
 #pragma unroll
-                        for (int wi = 1; wi < W; ++wi) wv = pick((k >> 5) == (uint32_t)wi, opp[m][wi], wv);
-                        const bool hit = in && h >= S && h < n && ((wv >> (k & 31u)) & 1u) != 0u;
+                            for (int wi = 1; wi < W; ++wi) wv = pick((k >> 5) == (uint32_t)wi, opp[m][wi], wv);
+                            hit = hit & (((wv >> (k & 31u)) & 1u) != 0u);
+                        }
                         sh |= hit ? 1u << h : 0u;
                     }
-                    bel[m] |= seeker[m] ? sh : 0u;
+                    bel[m] |= seeker[m] ? (sh & hmask) : 0u;
                 }
+                // A message to oneself ORs a belief into itself, and an absent
+                // agent (empty belief, never a target) sends nothing that
+                // counts, so neither needs a test.
                 uint32_t inc[TPL];
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) inc[m] = 0u;
@@ -1326,10 +1333,8 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     if constexpr (LANES > 1) pk = (uint32_t)__shfl((int)pk, q * LANES + i % LANES, 64);
                     const uint32_t ti = pk >> 27, bi = pk & 0x07ffffffu;
 #pragma unroll
-                    for (int m = 0; m < TPL; ++m) {
-                        const uint32_t a = (uint32_t)(l + m * LANES);
-                        inc[m] |= (i < n && ti == a && (uint32_t)i != a) ? bi : 0u;
-                    }
+                    for (int m = 0; m < TPL; ++m)
+                        inc[m] |= ti == (uint32_t)(l + m * LANES) ? bi : 0u;
                 }
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) bel[m] |= inc[m];

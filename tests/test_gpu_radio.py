@@ -194,3 +194,27 @@ def test_full_size_radio4k_sampled():
     g.close()
     del out
     torch.cuda.empty_cache()
+
+
+R = wl.DEFAULT_FLAGS | wl.RADIO
+EDGE = {
+    "max_agents_64x64_one_seeker": wl.spec(64, 64, 20, 4, 4, 10, S=1, flags=R),
+    "max_agents_64x64_one_hider": wl.spec(64, 64, 20, 4, 4, 10, S=19, flags=R | wl.OCCLUDE),
+    "no_seekers": wl.spec(16, 16, 6, 2, 3, 10, S=0, flags=R),
+    "no_hiders": wl.spec(16, 16, 6, 2, 3, 10, S=6, flags=R),
+    "alone": wl.spec(8, 8, 1, 1, 3, 10, S=1, flags=R),
+    "collisions_off": wl.spec(12, 12, 10, 2, 3, 5, flags=R & ~wl.COLLIDE),
+    "capture_ends_tiny": wl.spec(6, 6, 8, 3, 4, 0, S=4, flags=R, L=30),
+}
+
+
+@pytest.mark.parametrize("name", list(EDGE))
+def test_radio_edge_specs(name):
+    run_pair([EDGE[name]] * 67, seed=12, steps=160)
+
+
+@pytest.mark.parametrize("lanes", [[1, 2, 4, 8], [2, 4, 8, 16], [16, 16, 16, 16]])
+def test_radio_edge_specs_every_tiling(lanes):
+    specs = [s for s in EDGE.values() if s["H"] <= 16 or lanes[3] >= 8]
+    acts = wl.radio_actions(120, specs * 9, 15, draw_frac=0.3)
+    run_pair(specs * 9, seed=13, steps=120, actions=acts, lanes=lanes)

@@ -1320,22 +1320,34 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     }
                     bel[m] |= seeker[m] ? (sh & hmask) : 0u;
                 }
-                // A message to oneself ORs a belief into itself, and an absent
-                // agent (empty belief, never a target) sends nothing that
-                // counts, so neither needs a test.
+                // Each agent's belief and target (bits 0..19 and 27..31) go
+                // to word i of the env's respawn words (unused until a reset
+                // of this step; every word below NMAX is written by exactly
+                // one lane), and every lane reads them all back: independent
+                // LDS reads instead of one dependent cross-lane shuffle per
+                // agent. A message to oneself ORs a belief into itself, and
+                // an absent agent (empty belief, never a target) sends
+                // nothing that counts, so neither needs a test.
+                uint32_t *xw = (uint32_t *)spawned;
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int a = l + m * LANES;
+                    if (a < NMAX) xw[a] = bel[m] | (tgt_r[m] << 27);
+                }
+                wave_lds_fence();
                 uint32_t inc[TPL];
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) inc[m] = 0u;
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    // agent i is task i / LANES of lane i % LANES of the env
-                    uint32_t pk = bel[i / LANES] | (tgt_r[i / LANES] << 27);
-                    if constexpr (LANES > 1) pk = (uint32_t)__shfl((int)pk, q * LANES + i % LANES, 64);
+                    const uint32_t pk = xw[i];
                     const uint32_t ti = pk >> 27, bi = pk & 0x07ffffffu;
 #pragma unroll
                     for (int m = 0; m < TPL; ++m)
                         inc[m] |= ti == (uint32_t)(l + m * LANES) ? bi : 0u;
                 }
+                // the reads precede any respawn write to these words
+                wave_lds_fence();
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) bel[m] |= inc[m];
             }

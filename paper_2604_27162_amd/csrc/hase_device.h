@@ -1053,6 +1053,18 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 
         // One step from the generator's actions of this step (3 bits per
         // agent); all of its stores are issued together at the end.
+        // radio targets drawn for a window of steps (the windowed feature
+        // loop): lane l holds the RADIO block (step + wstep, group wgroup)
+        // mapped to four 5-bit targets; step rj of the window reads them
+        constexpr bool RWIN = RAD && WINDOWED && !DPP_WINDOW;
+        uint32_t rwin = 0u, rj = 0u;
+        auto block_targets = [&](uint32_t sub, uint32_t step) __attribute__((always_inline)) {
+            const U4 x = philox(env, (ST_RADIO << 24) | sub, step, 0u, k0, k1);
+            const uint32_t m = (uint32_t)n;
+            return range_map(x.x, m) | (range_map(x.y, m) << 5) | (range_map(x.z, m) << 10) |
+                   (range_map(x.w, m) << 15);
+        };
+
         auto step = [&](uint64_t acts) __attribute__((always_inline)) {
             // ---- 1 radio targets of this lane's tasks (own index: no
             // message): the RADIO draw, word a & 3 of block a >> 2, mapped
@@ -1062,10 +1074,19 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) {
                     const uint32_t a = (uint32_t)(l + m * LANES);
-                    const U4 x = philox(env, (ST_RADIO << 24) | (a >> 2), steps, 0u, k0, k1);
-                    const uint32_t w = pick((a & 2u) != 0u, pick((a & 1u) != 0u, x.w, x.z),
-                                            pick((a & 1u) != 0u, x.y, x.x));
-                    tgt_r[m] = range_map(w, (uint32_t)n);
+                    if constexpr (RWIN) {
+                        // block a >> 2 of this step sits in lane rj * ncalls +
+                        // (a >> 2) of the env (an absent agent may read another
+                        // lane's word: its target carries an empty belief)
+                        const uint32_t pkd = (uint32_t)__shfl(
+                            (int)rwin, q * LANES + (int)rj * ncalls + (int)(a >> 2), 64);
+                        tgt_r[m] = (pkd >> (5u * (a & 3u))) & 31u;
+                    } else {
+                        const U4 x = philox(env, (ST_RADIO << 24) | (a >> 2), steps, 0u, k0, k1);
+                        const uint32_t w = pick((a & 2u) != 0u, pick((a & 1u) != 0u, x.w, x.z),
+                                                pick((a & 1u) != 0u, x.y, x.x));
+                        tgt_r[m] = range_map(w, (uint32_t)n);
+                    }
                     if (has_act && (int)a < n) {
                         const int v = act_p[a];
                         if (v != -1) {
@@ -1492,9 +1513,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             // the same, one window of kb steps per outer iteration
             for (uint32_t left = nsteps; left != 0u;) {
                 const uint32_t win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                if constexpr (RWIN) rwin = block_targets((uint32_t)wgroup, steps + (uint32_t)wstep);
                 const uint32_t nw = left < (uint32_t)kb ? left : (uint32_t)kb;
 #pragma unroll 1
                 for (uint32_t j = 0; j < nw; ++j) {
+                    if constexpr (RWIN) rj = j;
                     uint64_t acts = 0;
 #pragma unroll
                     for (int g = 0; g < MAXCALLS; ++g) {

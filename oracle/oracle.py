@@ -259,13 +259,14 @@ class OracleBatch:
             self.belief[:self.agents_total] = st["belief"]
 
 
-def spawn(spec: dict, walls: np.ndarray, seed: int, env: int, episode: int):
-    """Positions the spawn rule gives one env (exported for spawn tests)."""
+def spawn(spec: dict, walls: np.ndarray, seed: int, env: int, episode: int, libpath=None):
+    """Positions the spawn rule gives one env (exported for spawn tests;
+    libpath: another build of the oracle, e.g. a planted mistake)."""
     sp = spec_table([spec])[0].copy()
     walls = np.ascontiguousarray(walls, dtype=np.uint8)
     px = np.zeros(int(spec["n"]), np.uint8)
     py = np.zeros(int(spec["n"]), np.uint8)
-    lib().or_spawn_env(sp.ctypes.data, walls.ctypes.data, px.ctypes.data, py.ctypes.data,
+    lib(libpath).or_spawn_env(sp.ctypes.data, walls.ctypes.data, px.ctypes.data, py.ctypes.data,
                        ctypes.c_uint64(seed), int(env), int(episode))
     return px, py
 

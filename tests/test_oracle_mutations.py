@@ -104,6 +104,17 @@ MUTATIONS = {
     "radio_beliefs_kept_at_reset": ("        for (int i = 0; i < n; ++i) bel[i] = 0;\n",
                                     "        for (int i = 0; i < n && 0; ++i) bel[i] = 0;\n"),
     "radio_belief_word_missing": ("oi[aw - 1] = belief[i];", "oi[aw - 1] = 0;"),
+    "spawn_agent_key_zero": ("OR_STREAM_SPAWN, (uint32_t)i, e, (uint32_t)j, 0), cells)",
+                             "OR_STREAM_SPAWN, 0u, e, (uint32_t)j, 0), cells)"),
+    "spawn_attempt_episode_swapped": ("OR_STREAM_SPAWN, (uint32_t)i, e, (uint32_t)j, 0), cells)",
+                                      "OR_STREAM_SPAWN, (uint32_t)i, (uint32_t)j, e, 0), cells)"),
+    "spawn_word_1": ("OR_STREAM_SPAWN, (uint32_t)i, e, (uint32_t)j, 0), cells)",
+                     "OR_STREAM_SPAWN, (uint32_t)i, e, (uint32_t)j, 1), cells)"),
+    "spawn_cap_63": ("for (int j = 0; j < OR_SPAWN_ATTEMPTS && !placed; ++j)",
+                     "for (int j = 0; j < OR_SPAWN_ATTEMPTS - 1 && !placed; ++j)"),
+    "spawn_cap_65": ("for (int j = 0; j < OR_SPAWN_ATTEMPTS && !placed; ++j)",
+                     "for (int j = 0; j <= OR_SPAWN_ATTEMPTS && !placed; ++j)"),
+    "spawn_scan_from_cell_0": ("uint32_t cc = (c + d) % cells;", "uint32_t cc = (d - 1) % cells;"),
 }
 
 
@@ -155,6 +166,7 @@ def run_pins(libpath, rocrand_philox):
     pins = [("golden", golden_pin), ("bruteforce", brute_pin), ("philox", philox_pin),
             ("streams", lambda: rng.check_stream_layout(rocrand_philox, libpath)),
             ("respawn", lambda: rng.check_respawn_keyed_by_episode(rocrand_philox, libpath)),
+            ("spawn", lambda: rng.check_spawn_rule(rocrand_philox, libpath)),
             ("explore_golden", lambda: explore.check_hand_worked(libpath)),
             ("explore_restated", lambda: explore.check_restated(False, libpath, n_envs=6, steps=60)),
             ("explore_restated_occluded",

@@ -179,3 +179,121 @@ def test_action_distribution_chi_square():
     chi2 = float(((counts - exp) ** 2 / exp).sum())
     assert chi2 < 18.47  # 0.999 quantile, 4 dof
     del sp
+
+
+# ---- the spawn rule beyond agent 0's first draw -------------------------------
+
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_WEYL = (0x9E3779B9, 0xBB67AE85)
+
+
+def philox_np(ctr, key):
+    """Philox4x32-10 blocks for many counters at once (numpy, vectorised over
+    rows of ctr [N, 4]; key = (k0, k1)). A third implementation, written
+    here for bulk draws and checked against rocRAND before every use."""
+    c = [np.asarray(ctr[:, i], np.uint64) for i in range(4)]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    m32 = np.uint64(0xFFFFFFFF)
+    for rnd in range(10):
+        p0 = np.uint64(PHILOX_M[0]) * c[0]
+        p1 = np.uint64(PHILOX_M[1]) * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & m32, (p0 >> np.uint64(32)) ^ c[3] ^ k1, p0 & m32]
+        k0 = (k0 + np.uint64(PHILOX_WEYL[0])) & m32
+        k1 = (k1 + np.uint64(PHILOX_WEYL[1])) & m32
+    return np.stack(c, axis=1)
+
+
+def spawn_restated(free, n, word):
+    """The spawn rule (reading R11) written out again: agent i tries the cells
+    floor(word(i, j) * cells / 2^32) for attempts j = 0..63 and takes the
+    first that is free and not held by an agent < i; when all 64 fail, it
+    takes the first such cell scanning row-major from the cell after its
+    last draw, wrapping. Returns the cells and, per agent, how it was placed:
+    the attempt index, or -1 for the scan."""
+    cells = len(free)
+    held, how = [], []
+    for i in range(n):
+        ok = lambda c: free[c] and c not in held  # noqa: E731
+        pick = None
+        for j in range(64):
+            c = (int(word(i, j)) * cells) >> 32
+            if ok(c):
+                pick = c
+                how.append(j)
+                break
+        if pick is None:
+            pick = next((c + d) % cells for d in range(1, cells + 1) if ok((c + d) % cells))
+            how.append(-1)
+        held.append(pick)
+    return held, how
+
+
+def test_spawn_rule_against_rocrand(rocrand_philox):
+    check_spawn_rule(rocrand_philox)
+
+
+def check_spawn_rule(rocrand_philox, libpath=None, n_envs=3000):
+    """Crowded 8x8 grids (n agents, n + 1 or n + 2 free cells, so later agents
+    reject most draws and often exhaust their 64 attempts): the oracle's
+    positions equal the restated rule fed with SPAWN words (counter
+    (env, 1 << 24 | agent, episode, attempt), word 0) for every agent, and the
+    cases that tell a wrong agent key, attempt cap or scan start apart from
+    the rule all occur."""
+    seed = 0x5EED0000ABCD1234
+    key = _key(seed)
+    g = np.random.Generator(np.random.PCG64(31))
+    # the bulk generator against rocRAND first
+    probe = g.integers(0, 2**30, size=(256, 4), dtype=np.uint64)
+    ref = rocrand_philox([key + [int(v) for v in r] for r in probe])
+    assert np.array_equal(philox_np(probe, key), ref)
+
+    H = W = 8
+    cells = H * W
+    cases = []
+    for _ in range(n_envs):
+        n = int(g.integers(2, 6))
+        free = np.zeros(cells, bool)
+        free[g.choice(cells, size=n + int(g.integers(1, 3)), replace=False)] = True
+        cases.append((n, free, int(g.integers(0, 2**31)), int(g.integers(0, 5000))))
+    # 65 attempts per agent: the 65th tells a cap of 65 apart
+    ctr = np.array([[env, (1 << 24) | i, ep, j] for n, _, env, ep in cases
+                    for i in range(n) for j in range(65)], np.uint64)
+    words = philox_np(ctr, key)[:, 0]
+    # spot check of the bulk words against rocRAND itself
+    pick = g.choice(len(ctr), size=200, replace=False)
+    assert np.array_equal(words[pick],
+                          rocrand_philox([key + [int(v) for v in ctr[k]] for k in pick])[:, 0])
+
+    seen = dict(later_agent_after_rejections=0, scan=0, scan_not_from_cell_0=0,
+                last_attempt=0, last_attempt_differs_from_scan=0, draw_65_differs_from_scan=0)
+    at = 0
+    for n, free, env, ep in cases:
+        wd = words[at:at + 65 * n].reshape(n, 65)
+        at += 65 * n
+        want, how = spawn_restated(free, n, lambda i, j: wd[i, j])
+        sp = wl.spec(H, W, n, 1, 3, 0, flags=0)
+        px, py = o.spawn(sp, (~free).astype(np.uint8), seed=seed, env=env, episode=ep,
+                         libpath=libpath)
+        got = (py.astype(int) * W + px).tolist()
+        assert got == want, (n, np.flatnonzero(free).tolist(), env, ep, got, want, how)
+        for i in range(n):
+            held = want[:i]
+            acceptable = [c for c in range(cells) if free[c] and c not in held]
+            last = (int(wd[i, 63]) * cells) >> 32
+            if i > 0 and how[i] > 0:
+                seen["later_agent_after_rejections"] += 1
+            if how[i] == -1:
+                seen["scan"] += 1
+                if acceptable[0] != want[i]:
+                    seen["scan_not_from_cell_0"] += 1
+                c65 = (int(wd[i, 64]) * cells) >> 32
+                if c65 in acceptable and c65 != want[i]:
+                    seen["draw_65_differs_from_scan"] += 1
+            if how[i] == 63:
+                seen["last_attempt"] += 1
+                prev = (int(wd[i, 62]) * cells) >> 32
+                scan62 = next((prev + d) % cells for d in range(1, cells + 1)
+                              if (prev + d) % cells in acceptable)
+                if scan62 != want[i]:
+                    seen["last_attempt_differs_from_scan"] += 1
+    assert all(v >= 2 for v in seen.values()), seen

@@ -42,7 +42,7 @@ extern "C" {
 #define HASE_OK 0
 #define HASE_EINVAL (-1)  /* bad spec or argument */
 #define HASE_ENOMEM (-2)  /* caller's state buffer smaller than required */
-#define HASE_EGRID (-3)   /* an env drew too few free cells for its agents */
+#define HASE_EGRID (-3)   /* an env has too few free cells for its agents */
 #define HASE_EHIP (-4)    /* HIP runtime error (detail in hase_last_error) */
 #define HASE_ESTATE (-5)  /* state arrays inconsistent with the batch */
 #define HASE_ENOTREADY (-6) /* step/observe before the first reset or set_state */
@@ -261,8 +261,9 @@ int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0);
  *   d_done     [n_steps][n_envs] uint8
  *   mode       HASE_STEP_PERSISTENT or HASE_STEP_PER_LAUNCH (identical results)
  * Enqueued on the stream; output buffers must not overlap the state. A
- * persistent call replays a captured graph with one kernel launch per
- * variant group (all n_steps inside); the groups sit on parallel branches
+ * persistent call runs all n_steps inside one kernel launch per variant
+ * group: a batch with one group launches its kernel directly; with several,
+ * the call replays a captured graph whose groups sit on parallel branches
  * and run concurrently.
  */
 int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
@@ -282,7 +283,9 @@ int hase_step_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uin
  * Capture (if not cached) the persistent step graph for exactly these
  * arguments without launching it, so a later persistent hase_step (or
  * hase_step_maps, with the same d_map) only replays it: no capture cost on
- * the critical path. Same argument rules as hase_step; enqueues nothing.
+ * the critical path (a batch with one variant group needs no graph: then
+ * only the arguments are checked). Same argument rules as hase_step;
+ * enqueues nothing.
  */
 int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
                  float *d_rew, uint8_t *d_done);
@@ -293,7 +296,10 @@ int hase_prepare_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, 
 int hase_observe(hase_batch *b, uint32_t *d_obs);
 
 /* Download / upload the full state (synchronises). set_state validates
- * positions (inside the map) and rebuilds the device-side bitboards. */
+ * positions (inside the map), tile values and, as hase_reset does for the
+ * grids it draws, that every env has room for its agents (at least n cells
+ * that each agent's class may stand on, else HASE_EGRID naming the first such
+ * env, and nothing is uploaded), then rebuilds the device-side bitboards. */
 int hase_get_state(hase_batch *b, const hase_host_state *out);
 int hase_set_state(hase_batch *b, const hase_host_state *in);
 

@@ -849,12 +849,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // inactive slots shadow the tile's first env and never store
     const uint32_t e = gp(J.tab.perm)[tile.env0 + (active ? (uint32_t)q : 0u)];
 
-    const uint32_t s0 = gp(J.tab.spec0)[e], s1 = gp(J.tab.spec1)[e], s2 = gp(J.tab.spec2)[e];
+    const uint32_t s0 = gp(J.tab.spec0)[e], s1 = gp(J.tab.spec1)[e];
     const int H = (int)(s0 & 0xffu), Wd = (int)((s0 >> 8) & 0xffu);
     const int n = (int)((s0 >> 16) & 0xffu), S = (int)(s0 >> 24);
     const int C = (int)((s1 >> 4) & 0xfu);
     const uint32_t flags = (s1 >> 8) & 0xffu, Lep = s1 >> 16;
-    const int P = (int)((s2 >> 8) & 0xffu);
     const bool collide = (flags & 1u) != 0u;
     const bool want_out = C == 4;
     constexpr bool FEAT_OK = KIND != KIND_PLAIN;
@@ -894,15 +893,26 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         if (K != 0u) map_load<LANES>(mslot, gp(J.disc) + map_off, H, Wd, l);
     }
     {
-        // rows of P words in HBM -> rows of LDS_ROW words (unused words 0);
-        // terrain envs have two planes, each one HBM board long
-        const GAS uint32_t *src = gp(J.bb) + gp(J.tab.bb_off)[e];
-        const int bw = (H + 2 * PAD) * LDS_ROW + 1;
-        const int hw = (H + 2 * PAD) * P + 1;
-        for (int i = l; i < (TER ? 2 * bw : bw); i += LANES) {
-            const int pl = i >= bw ? 1 : 0, j = i - pl * bw;
-            const int y = j / LDS_ROW, x = j - y * LDS_ROW;
-            slot[i] = x < P ? src[pl * hw + y * P + x] : 0u;
+        // The board planes are stored in HBM as they sit in LDS, 16-byte
+        // aligned and padded to 16 bytes: the env's lanes copy them 4 words
+        // per load, 8 loads in flight per lane before their stores (one
+        // memory round trip per batch instead of one per word).
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const GAS u32x4 *src = (const GAS u32x4 *)(gp(J.bb) + gp(J.tab.bb_off)[e]);
+        u32x4 *dst = (u32x4 *)slot;
+        const int n4 = board_words(H, TER ? 2 : 1) >> 2;
+        for (int base = 0; base < n4; base += 8 * LANES) {
+            u32x4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * LANES + l;
+                if (i < n4) v[u] = src[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * LANES + l;
+                if (i < n4) dst[i] = v[u];
+            }
         }
     }
     const uint32_t last_word = slot_words - 1u;

@@ -11,8 +11,10 @@ namespace hase {
 // two of them, the tile-type planes, one after the other): PAD cells of
 // "outside" on each side (PAD >= the largest view radius, so windows and move
 // targets never leave the board), bit x' of padded row y' in word
-// y' * P + (x' >> 5), P = ceil((W + 2 PAD) / 32). Cells outside the map read
-// as blocking, so a move check needs no separate bounds test.
+// y' * LDS_ROW + (x' >> 5) (the words past P = ceil((W + 2 PAD) / 32) of a row
+// are 0), then one slack word of ones. Cells outside the map read as
+// blocking, so a move check needs no separate bounds test. The layout in HBM
+// is the one the step kernel keeps in LDS, so staging a board is a plain copy.
 constexpr int PAD = 4;
 constexpr int MAX_AGENTS = 20;
 constexpr int MAX_SIDE = 64;
@@ -25,15 +27,20 @@ constexpr int BUCKET_NMAX[N_BUCKETS] = {2, 4, 10, 20};
 constexpr int MAX_VARIANTS = N_BUCKETS * PAD;
 
 inline int board_words_per_row(int W) { return (W + 2 * PAD + 31) >> 5; }
-// padded rows * words per row, plus one slack word so a two-word window read
-// at the last row stays inside the slot
-inline int board_words(int H, int W) { return (H + 2 * PAD) * board_words_per_row(W) + 1; }
 
-// In LDS every board row takes LDS_ROW words whatever the width (the widest
-// padded row, MAX_SIDE + 2 PAD = 72 cells, needs 3), so row offsets are
-// compile-time constants of the step kernel; plus one slack word.
+// Every board row takes LDS_ROW words whatever the width (the widest padded
+// row, MAX_SIDE + 2 PAD = 72 cells, needs 3), so row offsets are
+// compile-time constants of the step kernel; plus one slack word so a
+// two-word window read at the last row stays inside the board.
 constexpr int LDS_ROW = 3;
-inline int lds_board_words(int H) { return (H + 2 * PAD) * LDS_ROW + 1; }
+constexpr int lds_board_words(int H) { return (H + 2 * PAD) * LDS_ROW + 1; }
+
+// Words of an env's boards (planes of them, one after the other) rounded up
+// to a multiple of 4: in HBM every env's boards start 16-byte aligned and in
+// LDS every env slot does, so a lane stages 4 words per load and store.
+constexpr int round4(int v) { return (v + 3) & ~3; }
+constexpr int board_words(int H, int planes) { return round4(planes * lds_board_words(H)); }
+static_assert(MAX_AGENTS % 4 == 0, "LDS env slots are whole 16-byte units");
 
 // Packed per-env spec words.
 //   spec0 = H | W << 8 | n << 16 | S << 24

@@ -62,34 +62,36 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
     }
     __syncthreads();
 
-    // HBM board planes: rows of P words (plane 1 after plane 0, terrain
-    // only); the LDS copies used by the spawn below have rows of LDS_ROW
-    // words (unused words 0), as in the step kernel. Plane 0: wall or mud
+    // Board planes (plane 1 after plane 0, terrain only), rows of LDS_ROW
+    // words whose words past P are 0, then a slack word of ones, in HBM and in
+    // the LDS copies the spawn below reads, as in the step kernel; the HBM
+    // boards end with zero words up to a multiple of 4. Plane 0: wall or mud
     // (outside: 1), plane 1: water or mud (outside: 0).
     const int rows = H + 2 * PAD;
-    const int bw = rows * P + 1;
-    for (int i = lane; i < rows * LDS_ROW + 1; i += 64) board[0][i] = board[1][i] = 0u;
-    __syncthreads();
-    for (int pl = 0; pl < (terrain ? 2 : 1); ++pl) {
+    const int bw = rows * LDS_ROW + 1;
+    const int planes = terrain ? 2 : 1;
+    uint32_t *bb = A.bb + A.tab.bb_off[e];
+    for (int pl = 0; pl < planes; ++pl) {
         for (int i = lane; i < bw; i += 64) {
             uint32_t word = 0xffffffffu;  // slack word
-            const int yy = i / P, j = i - (i / P) * P;
-            if (i < rows * P) {
+            const int yy = i / LDS_ROW, j = i - yy * LDS_ROW;
+            if (i < rows * LDS_ROW) {
                 word = 0;
-                for (int b = 0; b < 32; ++b) {
+                for (int b = 0; b < 32 && j < P; ++b) {
                     const int xx = 32 * j + b;
                     const bool out = yy < PAD || yy >= H + PAD || xx < PAD || xx >= W + PAD;
                     bool v = pl == 0;
                     if (!out) v = ((cellw[(yy - PAD) * W + (xx - PAD)] >> pl) & 1u) != 0;
                     word |= (v ? 1u : 0u) << b;
                 }
-                board[pl][yy * LDS_ROW + j] = word;
-            } else {
-                board[pl][rows * LDS_ROW] = word;
             }
-            A.bb[A.tab.bb_off[e] + (uint32_t)(pl * bw + i)] = word;
+            board[pl][i] = word;
+            bb[pl * bw + i] = word;
         }
     }
+    for (int i = planes * bw + lane; i < round4(planes * bw); i += 64) bb[i] = 0u;
+    if (!terrain)
+        for (int i = lane; i < bw; i += 64) board[1][i] = 0u;
     __syncthreads();
     if (A.rebuild_only) return;
     if (flags & 16u) {

@@ -169,7 +169,7 @@ int make_plan(const hase_batch_desc *d, Plan &p)
         p.agents += s.n_agents;
         p.cells += (uint64_t)s.height * s.width;
         // terrain envs keep two board planes (tile types)
-        p.bb_words += (uint64_t)board_words(s.height, s.width) * ((s.flags & HASE_TERRAIN) ? 2 : 1);
+        p.bb_words += (uint64_t)board_words(s.height, (s.flags & HASE_TERRAIN) ? 2 : 1);
         if (s.flags & HASE_EXPLORE) p.map_words += (uint64_t)map_words(s.height, s.width);
     }
     if (p.obs_words >= (1ull << 32) || p.cells >= (1ull << 32) || p.bb_words >= (1ull << 32) ||
@@ -314,15 +314,17 @@ int build_tiles(hase_batch *b)
                     const uint32_t base = (uint32_t)perm.size();
                     for (uint32_t e : ids) {
                         perm.push_back(e);
+                        // LDS slots of whole 16-byte units (boards, respawn
+                        // words, discovery map)
                         if (p.specs[e].flags & HASE_EXPLORE) {
                             grp.xpl = true;
                             grp.map_words = std::max(
-                                grp.map_words, (uint32_t)lds_board_words(p.specs[e].height));
+                                grp.map_words, (uint32_t)round4(lds_board_words(p.specs[e].height)));
                         }
                         // terrain: two tile planes
                         const int planes = (p.specs[e].flags & HASE_TERRAIN) ? 2 : 1;
                         grp.slot_words = std::max(
-                            grp.slot_words, (uint32_t)(planes * lds_board_words(p.specs[e].height)));
+                            grp.slot_words, (uint32_t)board_words(p.specs[e].height, planes));
                     }
                     for (uint32_t i = 0; i < ids.size(); i += E) {
                         Tile t;
@@ -472,10 +474,15 @@ int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_
     return HASE_OK;
 }
 
-// One launch of the whole call: the captured graph (one kernel node per
-// variant group, groups on parallel branches) replayed on the stream.
+// One launch of the whole call. With several variant groups: the captured
+// graph (one kernel node per group, groups on parallel branches) replayed on
+// the stream. With one group the kernel is launched directly: a graph of one
+// node adds only the graph launch's host cost (measured under a runtime
+// trace: 32.7 us per hipGraphLaunch against 11.1 us per hipLaunchKernel),
+// which a call of a few steps waits for.
 int persistent_step(hase_batch *b, const JobDesc &job, uint32_t n_steps)
 {
+    if (b->variants.size() == 1) return enqueue(b, job, n_steps, 0, b->stream, false);
     hipGraphExec_t exec = nullptr;
     const int rc = graph_for(b, job, n_steps, &exec);
     if (rc) return rc;
@@ -768,6 +775,7 @@ int hase_prepare_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, 
 {
     const int rc = check_step_args(b, n_steps, d_obs, d_rew, d_done);
     if (rc) return rc;
+    if (b->variants.size() == 1) return HASE_OK;  // launched directly, no graph
     hipGraphExec_t exec = nullptr;
     return graph_for(b, make_job(b, d_actions, d_obs, d_rew, d_done, d_map), n_steps, &exec);
 }
@@ -830,10 +838,24 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
             pos[i] = (uint16_t)(in->pos_x[i] | (in->pos_y[i] << 8));
         }
         const uint8_t max_tile = (s.flags & HASE_TERRAIN) ? 3 : 1;
-        for (uint32_t c = 0; c < (uint32_t)s.height * s.width; ++c)
-            if (in->walls[p.grid_off[e] + c] > max_tile)
-                return fail(HASE_ESTATE, "env %u cell %u: tile value %u above %u", e, c,
-                            in->walls[p.grid_off[e] + c], max_tile);
+        // cells each agent class may stand on (plain envs: open cells, the
+        // walker's count): an auto-reset must find room for all n agents, as
+        // hase_reset demands of the grids it draws
+        uint32_t room[3] = {0, 0, 0};
+        for (uint32_t c = 0; c < (uint32_t)s.height * s.width; ++c) {
+            const uint8_t v = in->walls[p.grid_off[e] + c];
+            if (v > max_tile)
+                return fail(HASE_ESTATE, "env %u cell %u: tile value %u above %u", e, c, v, max_tile);
+            const bool terr = (s.flags & HASE_TERRAIN) != 0;
+            room[0] += terr ? (v == 0 || v == 3) : (v == 0);  // walker: ground, mud
+            room[1] += terr && v == 2;                       // swimmer: water
+            room[2] += terr && v != 1;                       // flyer: all but walls
+        }
+        for (uint32_t j = 0; j < s.n_agents; ++j) {
+            const uint32_t cls = (s.flags & HASE_TERRAIN) ? (uint32_t)(s.agent_classes >> (2 * j)) & 3u : 0u;
+            if (room[cls] < s.n_agents)
+                return fail(HASE_EGRID, "env %u has too few free cells for its agents", e);
+        }
         if (in->stuck && in->stuck[e] != 0u &&
             (!(s.flags & HASE_TERRAIN) || (in->stuck[e] >> s.n_agents) != 0u))
             return fail(HASE_ESTATE, "env %u: stuck bits of absent agents or without terrain", e);

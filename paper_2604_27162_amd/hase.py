@@ -193,9 +193,14 @@ class HaseBatch:
             return obs, rew, done, mp
         return obs, rew, done
 
-    def reset(self, seed: int):
-        obs0 = self.torch.empty(self.obs_words, dtype=self.torch.int32, device=self.device)
-        _check(load().hase_reset(self._h, ctypes.c_uint64(seed), obs0.data_ptr()))
+    def reset(self, seed: int, obs: bool = True):
+        """reset(seed); returns the first observation (None with obs=False:
+        then no observation is written)."""
+        obs0 = None
+        if obs:
+            obs0 = self.torch.empty(self.obs_words, dtype=self.torch.int32, device=self.device)
+        _check(load().hase_reset(self._h, ctypes.c_uint64(seed),
+                                 None if obs0 is None else obs0.data_ptr()))
         return obs0
 
     def _map_ptr(self, maps, n_steps: int):

@@ -173,6 +173,71 @@ def test_too_few_free_cells_is_reported():
     assert ei.value.code == hase.ENOTREADY
 
 
+def crowded_state(specs, seed):
+    """Host state of 8x8 envs with n + 1 or n + 2 open cells (agents on the
+    first n of them): every respawn rejects most draws and often scans."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    walls, px, py = [], [], []
+    for s in specs:
+        free = g.choice(64, size=s["n"] + int(g.integers(1, 3)), replace=False)
+        w = np.ones(64, np.uint8)
+        w[free] = 0
+        walls.append(w)
+        px += [int(c) % 8 for c in free[:s["n"]]]
+        py += [int(c) // 8 for c in free[:s["n"]]]
+    ne = len(specs)
+    return dict(walls=np.concatenate(walls), pos_x=np.array(px, np.uint8),
+                pos_y=np.array(py, np.uint8), found=np.zeros(ne, np.uint32),
+                t=np.zeros(ne, np.uint32), episode=g.integers(0, 1000, ne).astype(np.uint32),
+                steps=g.integers(0, 1000, ne).astype(np.uint32),
+                seed=g.integers(0, 2**63, ne).astype(np.uint64))
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_crowded_respawns(lanes):
+    """Episodes of one step on crowded 8x8 grids: every step respawns agents
+    that reject most draws, exhaust their 64 attempts and scan (the spawn
+    rule beyond agent 0's first draw), in every bucket."""
+    specs = [wl.spec(8, 8, n, 2, 4, 0, L=1) for n in (2, 3, 4, 6, 9, 10, 13, 20) for _ in range(23)]
+    st = crowded_state(specs, seed=lanes)
+    print(f"case: crowded respawns, lanes {lanes}", flush=True)
+    g = hase.HaseBatch(specs, env_id_base=3, device=DEV,
+                       lanes=[lanes, lanes, max(lanes, 4), max(lanes, 8)])
+    g.set_state(st)
+    ob = o.OracleBatch(specs, env_id_base=3)
+    ob.set_state(dict(st, env_id=np.arange(3, 3 + len(specs), dtype=np.uint32)))
+    gout = g.step(60)
+    torch.cuda.synchronize()
+    oout = ob.step(60)
+    assert_outputs(gout, oout, f"crowded lanes {lanes}")
+    assert_state(g, ob)
+    g.close()
+
+
+def test_set_state_without_room_is_rejected():
+    """A loaded grid with fewer open cells than agents is refused before any
+    step (an auto-reset could not place every agent)."""
+    specs = [wl.spec(8, 8, 4, 2, 4, 0, L=5)] * 6
+    st = crowded_state(specs, seed=1)
+    good = {k: v.copy() for k, v in st.items()}
+    w = st["walls"].reshape(6, 64)
+    # env 4: only 3 open cells for 4 agents (one agent's cell becomes a wall)
+    bad = np.flatnonzero(w[4] == 0)
+    w[4][bad[3:]] = 1
+    w[4][bad[:3]] = 0
+    st["pos_x"][4 * 4 + 3], st["pos_y"][4 * 4 + 3] = st["pos_x"][4 * 4], st["pos_y"][4 * 4]
+    g = hase.HaseBatch(specs, device=DEV)
+    with pytest.raises(hase.HaseError) as ei:
+        g.set_state(st)
+    assert ei.value.code == hase.EGRID and "env 4 " in str(ei.value)
+    with pytest.raises(hase.HaseError) as ei:
+        g.step(1)
+    assert ei.value.code == hase.ENOTREADY
+    g.set_state(good)
+    g.step(3)
+    g.close()
+
+
 def test_checkpoint_resume():
     specs = wl.workload_specs("uneven8k", 200)
     a = hase.HaseBatch(specs, device=DEV)

@@ -358,6 +358,22 @@ int hase_multi_workspace(hase_batch *const *batches, uint32_t n, uint64_t *bytes
 int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *d_workspace,
                     uint64_t workspace_bytes, void *stream);
 
+/*
+ * hase_step_multi without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation). Same arguments, results and launch
+ * behaviour as hase_step_multi; the job and tile tables go to a static
+ * device array of the library, HASE_STATIC_WORKSPACE_BYTES per GPU, held by
+ * every GPU the library runs on until the process ends. A call needing more
+ * (hase_multi_workspace) returns HASE_ENOMEM before any work is enqueued.
+ * The call allocates nothing. Every call on one GPU shares that GPU's array,
+ * which keeps the last call's tables: calls that overlap on one GPU (other
+ * streams, other host threads) race, so the caller serialises them (e.g.
+ * one stream, or an event between them).
+ */
+#define HASE_STATIC_WORKSPACE_BYTES (1u << 20)
+int hase_step_multi_static(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *stream);
+
 /* Release the handle (never frees caller memory). */
 int hase_destroy(hase_batch *b);
 

@@ -143,6 +143,11 @@ hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles
 
 hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 
+// Bytes of the library's static device workspace (per GPU) and the device
+// address of the current device's copy (looked up once per device).
+constexpr size_t STATIC_WORKSPACE_BYTES = 1u << 20;
+hipError_t static_workspace(void **ptr);
+
 // Per-lanes entry points, one translation unit each: single-variant and
 // mixed plain kernels (hase_step_l<L>.hip, hase_mixed_l<L>.hip), the line of
 // sight and exploration kinds (hase_feat_l<L>.hip) and the terrain kinds

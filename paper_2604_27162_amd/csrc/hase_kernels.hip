@@ -2,9 +2,41 @@
 // (the step-kernel variants live in hase_step_l*.hip, one file per lanes
 // value; their device code is in hase_device.h).
 
+#include <mutex>
+
 #include "hase_device.h"
 
 namespace hase {
+
+// ------------------------------------------------------------ static workspace
+
+// The device workspace of hase_step_multi_static: the job and tile tables of
+// a multi-batch step, for callers that cannot allocate device memory. Every
+// GPU holds its own copy of this array until the process ends. In host code
+// `scratch` names a host-side stand-in, not the device array: its device
+// address comes from hipGetSymbolAddress, looked up once per device with
+// that device current, and only that address is ever handed to HIP.
+static __device__ __align__(256) unsigned char scratch[STATIC_WORKSPACE_BYTES];
+
+hipError_t static_workspace(void **ptr)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 // ------------------------------------------------------------ init kernel
 

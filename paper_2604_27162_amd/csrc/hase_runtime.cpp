@@ -1099,6 +1099,25 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
     return HASE_OK;
 }
 
+int hase_step_multi_static(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *stream)
+{
+    if (n == 0) return HASE_OK;
+    if (!io) return fail(HASE_EINVAL, "null argument");
+    std::vector<hase_batch *> bs(n);
+    for (uint32_t i = 0; i < n; ++i) bs[i] = io[i].batch;
+    uint64_t need = 0;
+    const int rc = hase_multi_workspace(bs.data(), n, &need);
+    if (rc) return rc;
+    if (need > STATIC_WORKSPACE_BYTES)
+        return fail(HASE_ENOMEM,
+                    "these requests need %llu bytes of job and tile tables; the static workspace "
+                    "holds %zu (use hase_step_multi with a caller workspace)",
+                    (unsigned long long)need, STATIC_WORKSPACE_BYTES);
+    void *ws = nullptr;
+    HIP_TRY(static_workspace(&ws));
+    return hase_step_multi(io, n, n_steps, ws, STATIC_WORKSPACE_BYTES, stream);
+}
+
 int hase_destroy(hase_batch *b)
 {
     if (!b) return HASE_OK;

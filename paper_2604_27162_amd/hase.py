@@ -71,7 +71,8 @@ EXPORTS = ("hase_query_layout", "hase_create", "hase_get_offsets", "hase_get_map
            "hase_reset", "hase_step", "hase_step_maps", "hase_prepare", "hase_prepare_maps",
            "hase_observe", "hase_get_state", "hase_set_state", "hase_set_tiling",
            "hase_get_tiling", "hase_autotune", "hase_multi_workspace", "hase_step_multi",
-           "hase_destroy", "hase_strerror", "hase_last_error")
+           "hase_step_multi_static", "hase_destroy", "hase_strerror", "hase_last_error")
+STATIC_WORKSPACE_BYTES = 1 << 20
 
 _lib = None
 
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
         "hase_autotune": [vp, u32, vp, vp, vp, ctypes.POINTER(u32 * N_BUCKETS)],
         "hase_multi_workspace": [ctypes.POINTER(vp), u32, ctypes.POINTER(u64)],
         "hase_step_multi": [ctypes.POINTER(StepIO), u32, u32, vp, u64, vp],
+        "hase_step_multi_static": [ctypes.POINTER(StepIO), u32, u32, vp],
         "hase_destroy": [vp],
         "hase_strerror": [ctypes.c_int],
         "hase_last_error": [],
@@ -360,9 +362,7 @@ def multi_workspace_bytes(batches) -> int:
     return int(out.value)
 
 
-def step_multi(items, n_steps: int, workspace, stream) -> None:
-    """Enqueue one multi-batch step: items are (batch, steps, out_step0,
-    actions or None, obs, rew, done[, maps]) with per-batch device tensors."""
+def _step_ios(items):
     ios = (StepIO * max(1, len(items)))()
     for i, it in enumerate(items):
         b, k, s0, act, obs, rew, done = it[:7]
@@ -370,6 +370,21 @@ def step_multi(items, n_steps: int, workspace, stream) -> None:
         ios[i] = StepIO(b.handle.value, int(k), int(s0), None if act is None else act.data_ptr(),
                         obs.data_ptr(), rew.data_ptr(), done.data_ptr(),
                         None if mp is None else mp.data_ptr())
-    _check(load().hase_step_multi(ios, len(items), int(n_steps), workspace.data_ptr(),
+    return ios
+
+
+def step_multi(items, n_steps: int, workspace, stream) -> None:
+    """Enqueue one multi-batch step: items are (batch, steps, out_step0,
+    actions or None, obs, rew, done[, maps]) with per-batch device tensors."""
+    _check(load().hase_step_multi(_step_ios(items), len(items), int(n_steps),
+                                  workspace.data_ptr(),
                                   workspace.numel() * workspace.element_size(),
                                   ctypes.c_void_p(stream.cuda_stream)))
+
+
+def step_multi_static(items, n_steps: int, stream) -> None:
+    """step_multi with the library's static device workspace (no workspace
+    argument; the call allocates nothing; calls on one GPU must not overlap)."""
+    _check(load().hase_step_multi_static(_step_ios(items), len(items), int(n_steps),
+                                         ctypes.c_void_p(stream.cuda_stream)))
+

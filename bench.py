@@ -78,13 +78,16 @@ def map_bytes(s) -> int:
     return 4 * s["H"] * ((s["W"] + 31) // 32) if s["flags"] & EXPLORE else 0
 
 
-def out_bytes_per_step(specs, maps: bool = False, actions: bool = False) -> int:
+def out_bytes_per_step(specs, maps: bool = False, actions: bool = False,
+                       state: bool = False) -> int:
     """Algorithmic bytes of one step: packed obs words, one float32 reward
     per agent, one uint8 done per env and, with map output, the discovery
     maps of exploring envs; radio envs add a belief word per agent; external
-    actions add one int8 read per agent."""
+    actions add one int8 read per agent; the true-state output adds a uint16
+    position per agent and four uint32 words per env."""
     return sum(4 * s["n"] * (s["C"] * words(s["r"]) + (1 if s["flags"] & RADIO else 0)) +
-               4 * s["n"] + 1 + (map_bytes(s) if maps else 0) + (s["n"] if actions else 0)
+               4 * s["n"] + 1 + (map_bytes(s) if maps else 0) + (s["n"] if actions else 0) +
+               ((2 * s["n"] + 16) if state else 0)
                for s in specs)
 
 
@@ -92,18 +95,19 @@ def state_bytes_per_launch(specs) -> int:
     """Bytes a launch must read and write once: per-env spec/offset/key words
     and counters (read 56 B, plus the map offset for envs with line of sight
     or exploration; write 16 B), agent positions (2 B each way), the padded
-    wall bitboard (read; two tile planes with terrain, plus its 24 B of
+    board planes (read, as stored: rows of 3 words; two tile planes with terrain, plus its 24 B of
     classes and chances and the stuck word both ways) and the discovery map
     of an exploring env (read and write); radio envs read and write a belief
     word per agent."""
     tot = 0
     for s in specs:
-        P = (s["W"] + 8 + 31) // 32
-        board = 4 * ((s["H"] + 8) * P + 1)
+        planes = 2 if s["flags"] & TERRAIN else 1
+        # rows of 3 words, a slack word, padded to 16 bytes (as staged)
+        board = 4 * ((planes * ((s["H"] + 8) * 3 + 1) + 3) // 4 * 4)
         feat = 4 if s["flags"] & (8 | EXPLORE) else 0
         if s["flags"] & TERRAIN:
-            # second tile plane, terrain words (24 B), stuck word both ways
-            feat, board = feat + 24 + 8, 2 * board
+            # terrain words (24 B), stuck word both ways
+            feat += 24 + 8
         if s["flags"] & RADIO:
             feat += 8 * s["n"]
         tot += 56 + feat + 16 + 4 * s["n"] + board + 2 * map_bytes(s)
@@ -248,6 +252,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-maps", action="store_true",
                     help="exploring workloads: skip the per-step discovery-map output")
+    ap.add_argument("--true-state", choices=("on", "off", "auto"), default="auto",
+                    help="the per-step true-state output (positions, found / t / episode / "
+                         "stuck); auto: on for the exploring workload, whose per-step "
+                         "discovery maps and true state form the centralised observation")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (calibrates the "
                          "HBM traffic counters) and exit")
@@ -286,11 +294,13 @@ def main():
     if args.autotune:
         lanes = g.autotune(args.autotune)
     maps_on = g.map_words > 0 and not args.no_maps
+    state_on = args.true_state == "on" or (args.true_state == "auto" and g.map_words > 0)
     obs, rew, done = g.alloc_outputs(R)
     mp = g.alloc_outputs(R, maps=True)[3] if maps_on else None
-    g.prepare(obs, rew, done, R, maps=mp)
+    st = g.alloc_state_outputs(R) if state_on else None
+    g.prepare(obs, rew, done, R, maps=mp, state=st)
     for _ in range(W):
-        g.step_into(obs, rew, done, R, maps=mp)
+        g.step_into(obs, rew, done, R, maps=mp, state=st)
     torch.cuda.synchronize()
 
     # ---- K runs back to back, an event between consecutive runs
@@ -299,7 +309,7 @@ def main():
     t0 = time.perf_counter()
     evs[0].record(stream)
     for k in range(K):
-        g.step_into(obs, rew, done, R, maps=mp)
+        g.step_into(obs, rew, done, R, maps=mp, state=st)
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall_s = time.perf_counter() - t0
@@ -308,7 +318,7 @@ def main():
     mean_ms = total_ms / K
     value = agents * R * K / (total_ms / 1e3)
 
-    alg_bytes = R * out_bytes_per_step(specs, maps_on) + state_bytes_per_launch(specs)
+    alg_bytes = R * out_bytes_per_step(specs, maps_on, state=state_on) + state_bytes_per_launch(specs)
     achieved = alg_bytes / (mean_ms / 1e3) / 1e9
     line = {
         "metric": METRIC,
@@ -326,7 +336,8 @@ def main():
         "config": {"workload": f"{args.workload}: {DESCR[args.workload]}, {R} env-steps per run",
                    "n_envs": n_envs, "agents": agents, "env_steps_per_bench_step": R,
                    "launch": "persistent: one kernel launch per run (per lanes group)",
-                   "lanes_per_env": g.get_tiling(), "map_output": maps_on},
+                   "lanes_per_env": g.get_tiling(), "map_output": maps_on,
+                   "true_state_output": state_on},
         "env_steps_per_s": n_envs * R * K / (total_ms / 1e3),
         "run_ms": spread(run_ms),
         "wall_s_timed_region": wall_s,
@@ -365,11 +376,11 @@ def main():
         P = min(R, 2000)
         g2 = hase.HaseBatch(specs, device="cuda:0", lanes=lanes)
         g2.reset(w["seed"], obs=False)
-        g2.step_into(obs, rew, done, min(P, 50), mode=hase.PER_LAUNCH, maps=mp)
+        g2.step_into(obs, rew, done, min(P, 50), mode=hase.PER_LAUNCH, maps=mp, state=st)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        g2.step_into(obs, rew, done, P, mode=hase.PER_LAUNCH, maps=mp)
+        g2.step_into(obs, rew, done, P, mode=hase.PER_LAUNCH, maps=mp, state=st)
         e1.record(stream)
         torch.cuda.synchronize()
         ms_pl = e0.elapsed_time(e1)
@@ -380,26 +391,27 @@ def main():
 
         # ---- external int8 actions resident in HBM (one run)
         acts = torch.randint(0, 5, (R, agents), dtype=torch.int8, device="cuda:0")
-        g.prepare(obs, rew, done, R, actions=acts, maps=mp)
-        g.step_into(obs, rew, done, R, actions=acts, maps=mp)
+        g.prepare(obs, rew, done, R, actions=acts, maps=mp, state=st)
+        g.step_into(obs, rew, done, R, actions=acts, maps=mp, state=st)
         ms = []
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         for _ in range(3):
             torch.cuda.synchronize()
             e0.record(stream)
-            g.step_into(obs, rew, done, R, actions=acts, maps=mp)
+            g.step_into(obs, rew, done, R, actions=acts, maps=mp, state=st)
             e1.record(stream)
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         sp = spread(ms)
-        ab = R * out_bytes_per_step(specs, maps_on, actions=True) + state_bytes_per_launch(specs)
+        ab = (R * out_bytes_per_step(specs, maps_on, actions=True, state=state_on) +
+              state_bytes_per_launch(specs))
         line["int8_actions"] = dict(value=agents * R / (sp["median"] / 1e3), run_ms=sp,
                                     unit="agent-steps/s", alg_bytes_per_launch=ab,
                                     hbm_frac=ab / (sp["median"] / 1e3) / 1e9 / HBM_PEAK_GBS)
         del acts
 
         # ---- the same roofline against a copy measured on this GPU
-        del obs, rew, done, mp
+        del obs, rew, done, mp, st
         torch.cuda.empty_cache()
         cbw = copy_bandwidth(torch)
         roof["copy_gbs"] = cbw

@@ -280,6 +280,39 @@ int hase_step_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uin
                    float *d_rew, uint8_t *d_done, uint32_t *d_map, uint32_t mode);
 
 /*
+ * Every output of a step call (observability modes of Sec. 3.3: the
+ * decentralised windows alone, or with the centralised discovery map, each
+ * with or without the omniscient true state):
+ *   obs, rew, done  as for hase_step (required)
+ *   map        as for hase_step_maps, or NULL
+ *   pos        [n_steps][agents_total] uint16, or NULL: every agent's cell
+ *              x | y << 8 after the step (after a same-step auto-reset: the
+ *              respawned cell), agent i of env e at agent_off[e] + i
+ *   env_state  [n_steps][n_envs][4] uint32, or NULL: per env after the step
+ *              found (bit h: hider h found this episode), t (steps elapsed in
+ *              the episode), episode (episodes ended since the reset) and
+ *              stuck (bit i: agent i stuck; terrain envs, else 0); the same
+ *              values hase_get_state returns, row by row
+ * The true state is the state the next step starts from; with the
+ * observations it is what a centralised critic or the with-true-state
+ * observability modes read.
+ */
+typedef struct hase_outputs {
+    uint32_t *obs;
+    float *rew;
+    uint8_t *done;
+    uint32_t *map;
+    uint16_t *pos;
+    uint32_t *env_state;
+} hase_outputs;
+
+/* hase_step with any subset of the optional outputs (same argument rules,
+ * launch behaviour and results; hase_step and hase_step_maps are this call
+ * with pos and env_state NULL). */
+int hase_step_outputs(hase_batch *b, uint32_t n_steps, const int8_t *d_actions,
+                      const hase_outputs *out, uint32_t mode);
+
+/*
  * Capture (if not cached) the persistent step graph for exactly these
  * arguments without launching it, so a later persistent hase_step (or
  * hase_step_maps, with the same d_map) only replays it: no capture cost on
@@ -291,6 +324,8 @@ int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint3
                  float *d_rew, uint8_t *d_done);
 int hase_prepare_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
                       float *d_rew, uint8_t *d_done, uint32_t *d_map);
+int hase_prepare_outputs(hase_batch *b, uint32_t n_steps, const int8_t *d_actions,
+                         const hase_outputs *out);
 
 /* Observation of the current state (e.g. after hase_set_state); enqueued. */
 int hase_observe(hase_batch *b, uint32_t *d_obs);
@@ -357,6 +392,99 @@ typedef struct hase_step_io {
 int hase_multi_workspace(hase_batch *const *batches, uint32_t n, uint64_t *bytes);
 int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *d_workspace,
                     uint64_t workspace_bytes, void *stream);
+
+/*
+ * Arena: resident env slots for serving (continuous batching). An arena of
+ * n_slots slots, each with room for one env of at most max_height x
+ * max_width cells and max_agents agents, lives in one caller buffer of
+ * hase_query_arena bytes. A request is admitted into a range of free slots
+ * with hase_reset_range, stepped with every other admitted range by
+ * hase_step_resident, and leaves with hase_release_range; all three only
+ * enqueue work on the arena's stream (no host synchronisation), so the
+ * admission of one request overlaps the steps of the others. max_ranges
+ * bounds the ranges admitted at once.
+ */
+typedef struct hase_arena_desc {
+    uint32_t n_slots;
+    uint16_t max_height, max_width;
+    uint8_t max_agents;
+    uint32_t max_ranges;
+} hase_arena_desc;
+
+/* A range's own output buffers (caller device memory, laid out as the
+ * outputs of a uniform batch of `count` envs of the range's spec, env i of
+ * the range at the place of env i):
+ *   obs   [step_budget][count * n * (C * w + b)] uint32
+ *   rew   [step_budget][count * n] float32
+ *   done  [step_budget][count] uint8
+ *   map   [step_budget][count * H * ceil(W/32)] uint32, or NULL (exploring
+ *         specs only; NULL: no map output)
+ *   obs0  [count * n * (C * w + b)] uint32: the observation after the
+ *         reset, or NULL
+ *   err   one uint32 in device or pinned host memory, or NULL: written in
+ *         stream order after the reset, 0xffffffff when every env of the
+ *         range had room for its agents, else the index within the range of
+ *         the first env that had not (as hase_range_error, without a host
+ *         synchronisation)
+ *   pos, env_state  the true state after each step (hase_outputs), laid out
+ *         for the range's count envs, or NULL
+ * Row k of obs, rew, done, map, pos and env_state is the range's k-th step
+ * since its reset. */
+typedef struct hase_out_ptrs {
+    uint32_t *obs;
+    float *rew;
+    uint8_t *done;
+    uint32_t *map;
+    uint32_t *obs0;
+    uint32_t *err;
+    uint16_t *pos;
+    uint32_t *env_state;
+} hase_out_ptrs;
+
+/* Device bytes of an arena (validates the descriptor: n_slots >= 1, sides
+ * 2..64, max_agents 1..20, max_ranges 1..65536). */
+int hase_query_arena(const hase_arena_desc *desc, uint64_t *state_bytes);
+
+/* Create an arena over caller memory d_state (>= hase_query_arena bytes,
+ * 256-byte aligned) on stream (a hipStream_t or NULL). Uploads the slot
+ * tables (synchronously); every slot starts free. */
+int hase_create_arena(const hase_arena_desc *desc, void *d_state, uint64_t state_bytes,
+                      void *stream, hase_batch **out);
+
+/*
+ * Admit a request into slots [first_slot, first_slot + count), which must lie
+ * inside the arena and be free: every env gets `spec` (fitting the arena's
+ * caps), generator seed `seed` and env id env_id_base + i for slot
+ * first_slot + i, and is reset exactly as hase_reset resets a batch (walls,
+ * spawn, desync; Sec. 4.2 resets, Sec. 3.3 desynchronised start), so a
+ * range reproduces the batch hase_create + hase_reset would make of it. The
+ * range then takes step_budget >= 1 steps through hase_step_resident,
+ * writing them to *out (copied; the buffers must stay valid until the range
+ * is released), and stops. Enqueued on the arena's stream; nothing
+ * synchronises. An env with too few free cells for its agents (HASE_EGRID
+ * at hase_reset) does not fail the call: hase_range_error reports it, and
+ * the range's outputs are then meaningless. Errors (synchronous, before any
+ * work): HASE_EINVAL for a bad spec, a spec beyond the caps, slots outside
+ * the arena or taken, a zero budget, null output buffers, no free range.
+ */
+int hase_reset_range(hase_batch *arena, uint32_t first_slot, uint32_t count,
+                     const hase_env_spec *spec, uint64_t seed, uint32_t env_id_base,
+                     uint32_t step_budget, const hase_out_ptrs *out);
+
+/* Every admitted range takes min(n_steps, steps left of its budget) steps
+ * (the step of hase_step, persistent: one kernel launch per group of ranges
+ * with the same env kind and lanes per env, groups concurrent). Enqueued. */
+int hase_step_resident(hase_batch *arena, uint32_t n_steps);
+
+/* Release the range starting at first_slot: its slots are free for another
+ * hase_reset_range, and later steps leave it alone (enqueued, in stream
+ * order after the steps before it). */
+int hase_release_range(hase_batch *arena, uint32_t first_slot);
+
+/* The range's reset check (synchronises the stream): *bad_env = -1 when every
+ * env had room for its agents, else the first env (index within the range)
+ * that had not. */
+int hase_range_error(hase_batch *arena, uint32_t first_slot, int64_t *bad_env);
 
 /*
  * hase_step_multi without a workspace argument, for callers that cannot

@@ -135,6 +135,12 @@ __device__ __forceinline__ void spawn_agents_if(int *out, int n, int H, int W, u
                 placed = true;
             }
         }
+        // No room at all (only an arena range reported failed at its reset
+        // gets here): the agent takes its last drawn cell, inside the map.
+        if (!placed) {
+            const uint32_t y = c / (uint32_t)W, xx = c - y * (uint32_t)W;
+            out[i] = (int)(((y + PAD) << 8) | (xx + PAD));
+        }
     }
 }
 
@@ -861,11 +867,33 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     constexpr bool TER = (KIND & KIND_TERRAIN) != 0;  // every env of the tile has terrain
     constexpr bool RAD = (KIND & KIND_RADIO) != 0;    // every env of the tile has radio
 
-    const uint32_t obs_off = gp(J.tab.obs_off)[e], agent_off = gp(J.tab.agent_off)[e];
+    // agent_off: the env's agents in the state (positions, beliefs)
+    const uint32_t agent_off = gp(J.tab.agent_off)[e];
     const uint32_t env = gp(J.tab.env_id)[e];
     const uint64_t seed = gp(J.seed)[e];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     uint32_t found = gp(J.found)[e], t = gp(J.t)[e], ep = gp(J.ep)[e], steps = gp(J.steps)[e];
+    // Output places: the job's first output row, its step limit, and the
+    // env's first obs word, first reward (and action) and done byte in a
+    // row. A resident range writes row = the env's step count since its
+    // reset (the same for every env of the range, so for the whole tile),
+    // relative to the range's first env, and stops at its budget.
+    // The step count and limit stay wave-uniform (scalar registers): a
+    // per-lane trip count would turn the step loop into a divergent one.
+    uint32_t out_step0 = J.out_step0, k_limit = J.k_limit;
+    uint32_t obs_off, out_agent = agent_off, out_env = e;
+    if (J.resident) {
+        const uint32_t rel = e - J.first;
+        const uint32_t s_wave = __builtin_amdgcn_readfirstlane(steps);
+        out_step0 = s_wave;
+        k_limit = J.budget > s_wave ? J.budget - s_wave : 0u;
+        obs_off = rel * J.obs_env;
+        out_agent = rel * (uint32_t)n;
+        out_env = rel;
+        if (K != 0u && k_limit == 0u) return;  // the range has taken its budget
+    } else {
+        obs_off = gp(J.tab.obs_off)[e];
+    }
     // terrain: the second tile plane pw words after the first, the stuck
     // chance (bits 16..23 of word 0), the move chances (bytes of words 1..3,
     // class * 3 + tile), the agent classes (words 4, 5) and the stuck agents
@@ -938,22 +966,29 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     const int kb = WINDOWED ? LANES / ncalls : 1;  // steps per action window
     // in a window, lane l draws block (step + wstep, group wgroup)
     const int wstep = WINDOWED ? l / ncalls : 0, wgroup = WINDOWED ? l - wstep * ncalls : 0;
-    const uint32_t Kj = K < J.k_limit ? K : J.k_limit;
+    const uint32_t Kj = K < k_limit ? K : k_limit;
     const bool obs_only = (K == 0);
     const uint32_t nsteps = obs_only ? 1u : Kj;
 
-    GAS uint32_t *obs_p = gp(J.obs) + ((uint64_t)J.out_step0 + step_base) * J.obs_stride + obs_off;
-    GAS float *rew_p = obs_only ? nullptr
-                                : gp(J.rew) + ((uint64_t)J.out_step0 + step_base) * J.agent_stride + agent_off;
-    GAS uint8_t *done_p = obs_only ? nullptr
-                                   : gp(J.done) + ((uint64_t)J.out_step0 + step_base) * J.env_stride + e;
-    const GAS int8_t *act_p =
-        J.act ? gp(J.act) + ((uint64_t)J.out_step0 + step_base) * J.agent_stride + agent_off : nullptr;
+    const uint64_t row = (uint64_t)out_step0 + step_base;
+    GAS uint32_t *obs_p = gp(J.obs) + row * J.obs_stride + obs_off;
+    GAS float *rew_p = obs_only ? nullptr : gp(J.rew) + row * J.agent_stride + out_agent;
+    GAS uint8_t *done_p = obs_only ? nullptr : gp(J.done) + row * J.env_stride + out_env;
+    const GAS int8_t *act_p = J.act ? gp(J.act) + row * J.agent_stride + out_agent : nullptr;
+    // the true state after each step, when requested (a wave-uniform test)
+    const bool want_state = J.spos != nullptr && !obs_only;
+    GAS uint16_t *spos_p = (J.spos != nullptr && !obs_only) ? gp(J.spos) + row * J.agent_stride + out_agent
+                                                             : nullptr;
+    GAS uint32_t *senv_p = (J.senv != nullptr && !obs_only)
+                               ? gp(J.senv) + (row * J.env_stride + out_env) * 4u
+                               : nullptr;
     // per-step discovery maps of an active exploring env, when requested
     GAS uint32_t *map_p = nullptr;
     if constexpr (XPL) {
-        if (active && J.map != nullptr && !obs_only)
-            map_p = gp(J.map) + ((uint64_t)J.out_step0 + step_base) * J.map_stride + map_off;
+        if (active && J.map != nullptr && !obs_only) {
+            const uint32_t map_out = J.resident ? (e - J.first) * J.map_env : map_off;
+            map_p = gp(J.map) + row * J.map_stride + map_out;
+        }
     }
 
     // Complete every load issued so far here, before the step loop: the wait
@@ -1452,6 +1487,28 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     map_p += J.map_stride;
                 }
             }
+            // ---- 8 the true state after the step (observability modes with
+            // the true state): positions, then found / t / episode / stuck
+            if (want_state) {
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    if (mine_live[m]) {
+                        const uint32_t pc = (uint32_t)mine[m];
+                        spos_p[l + m * LANES] = (uint16_t)(((pc & 0xffu) - PAD) | (((pc >> 8) - PAD) << 8));
+                    }
+                }
+                if (active && l == 0) {
+                    typedef uint32_t u32x4s __attribute__((ext_vector_type(4)));
+                    u32x4s v;
+                    v.x = found;
+                    v.y = t;
+                    v.z = ep;
+                    v.w = stuck;
+                    *(GAS u32x4s *)senv_p = v;
+                }
+                spos_p += J.agent_stride;
+                senv_p += J.env_stride * 4u;
+            }
             steps += 1u;
 #pragma unroll
             for (int m = 0; m < TPL; ++m) {
@@ -1640,8 +1697,11 @@ __global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__
     extern __shared__ uint32_t lds[];
     if (blockIdx.x >= n_tiles) return;
     const Tile tile = tiles[blockIdx.x];
+    // arena launches run one group over the whole tile table, whose other
+    // entries belong to other groups or are empty
+    if (tile.count == 0u || (job0.group != ALL_GROUPS && (tile.variant >> 8) != job0.group)) return;
     const JobDesc J = jobs ? jobs[tile.job] : job0;
-    const int bucket = (int)(tile.variant >> 2), r = (int)(tile.variant & 3u) + 1;
+    const int bucket = (int)((tile.variant >> 2) & 3u), r = (int)(tile.variant & 3u) + 1;
     switch (bucket) {
     case 0: mixed_bucket<LANES, 0, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
     case 1: mixed_bucket<LANES, 1, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;

@@ -85,14 +85,32 @@ struct JobDesc {
     uint32_t *map;        // per-step map output, may be null
     uint64_t map_stride;  // map words per output step
     uint32_t *bel;        // per-agent hider beliefs (radio), at tab.agent_off[e]
+    // the true state after each step (may be null): agent positions x | y << 8
+    // per output row (agent_stride entries, the rewards' places), and per env
+    // four words found, t, episode, stuck (env_stride * 4 words per row)
+    uint16_t *spos;
+    uint32_t *senv;
+    // A resident range of an arena (resident = 1): envs [first, first + count)
+    // of one spec, outputs relative to the range (env first + i writes obs
+    // words from i * obs_env, rewards from i * n, done byte i, map words from
+    // i * map_env), the output row of a step is the env's step count since
+    // the range's reset, and the range stops after budget steps.
+    uint32_t resident, first, budget, obs_env, map_env;
+    // launch filter (read from the kernel's by-value job only): a wave steps
+    // its tile only if the tile's group (variant >> 8) equals group;
+    // 0xffffffff steps every tile
+    uint32_t group;
 };
 
 // A wave's work: envs perm[env0 .. env0 + count) of job `job` (count <= 64 /
-// lanes); variant = agent-count bucket * 4 + view radius - 1 (read by the
-// mixed-variant kernel).
+// lanes; 0: an empty tile, skipped); variant = agent-count bucket * 4 + view
+// radius - 1 (read by the mixed-variant kernel), plus, for the tiles of an
+// arena, the launch group (env kind | lanes << 8) in bits 8 and up.
 struct Tile {
     uint32_t job, env0, count, variant;
 };
+constexpr uint32_t ALL_GROUPS = 0xffffffffu;
+constexpr uint32_t group_code(int kind, int lanes) { return (uint32_t)kind | ((uint32_t)lanes << 8); }
 
 struct InitArgs {
     EnvTables tab;
@@ -104,11 +122,29 @@ struct InitArgs {
     uint32_t *disc;       // discovery maps, cleared at reset
     uint32_t *stuck;      // stuck agents, cleared at reset
     uint32_t *bel;        // per-agent beliefs, cleared at reset
-    uint32_t *err;        // min over envs with too few free cells (reset only)
+    uint32_t *err;        // min over envs with too few free cells (reset only), minus env0
     uint64_t seed_value;
+    uint32_t env0;        // block b resets env env0 + b
     uint32_t n_envs;
     uint32_t rebuild_only; // 1: walls/positions already loaded, only rebuild bitboards
 };
+
+// Setup of an arena range (one kernel, by-value arguments): the per-slot
+// spec words, terrain words and env ids of slots [first, first + count),
+// their tiles (tile i of the range at tile index first + i, the rest of the
+// range's tile entries emptied), the range's job descriptor and error word.
+// With clear = 1 only the tile entries of the slots are emptied (release).
+struct RangeArgs {
+    uint32_t *spec0, *spec1, *spec2, *terr, *env_id;
+    Tile *tiles;
+    JobDesc *jobs;
+    uint32_t *job_err;
+    JobDesc job;
+    uint32_t job_index, first, count, clear;
+    uint32_t s0, s1, s2, env_id_base, lanes, variant;
+    uint32_t terr_words[8];
+};
+hipError_t launch_range(const RangeArgs &a, hipStream_t stream);
 
 // Env kinds: each kind has its own step loop and its own kernels (so the
 // register allocation of one never burdens another), and a tile holds envs

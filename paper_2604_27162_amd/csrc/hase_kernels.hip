@@ -49,7 +49,7 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
     __shared__ uint8_t cellw[MAX_SIDE * MAX_SIDE];
     __shared__ uint32_t board[2][(MAX_SIDE + 2 * PAD) * LDS_ROW + 1];
     __shared__ int spawned[MAX_AGENTS];
-    const uint32_t e = blockIdx.x;
+    const uint32_t e = A.env0 + blockIdx.x;
     const int lane = (int)threadIdx.x;
     const uint32_t s0 = A.tab.spec0[e], s1 = A.tab.spec1[e], s2 = A.tab.spec2[e];
     const int H = (int)(s0 & 0xffu), W = (int)((s0 >> 8) & 0xffu);
@@ -148,7 +148,17 @@ __global__ __launch_bounds__(64) void init_kernel(InitArgs A)
         room = room && (c == 0u ? f[0] : (c == 1u ? f[1] : f[2])) >= n;
     }
     if (!room) {
-        if (lane == 0) atomicMin(A.err, e);
+        if (lane == 0) {
+            atomicMin(A.err, e - A.env0);
+            // a batch with such an env is refused; an arena range with one
+            // is reported failed but may still be stepped until released, so
+            // its agents get cells inside the map (the first cell)
+            const uint32_t ao = A.tab.agent_off[e];
+            for (int j = 0; j < n; ++j) A.pos[ao + (uint32_t)j] = 0;
+            A.seed[e] = A.seed_value;
+            A.found[e] = A.t[e] = A.ep[e] = A.steps[e] = A.stuck[e] = 0;
+            for (int j = 0; j < n; ++j) A.bel[ao + (uint32_t)j] = 0u;
+        }
         return;
     }
     if (lane == 0) {
@@ -238,6 +248,47 @@ hipError_t launch_init(const InitArgs &a, hipStream_t stream)
 {
     if (a.n_envs == 0) return hipSuccess;
     hipLaunchKernelGGL(init_kernel, dim3(a.n_envs), dim3(64), 0, stream, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ arena ranges
+
+// One thread per slot of the range: its spec words, terrain words and env
+// id, and its tile entry (slot first + i holds tile i of the range while i <
+// the range's tile count, else an empty entry); thread 0 also writes the
+// range's job descriptor and clears its error word. With clear, only the
+// tile entries are emptied.
+__global__ __launch_bounds__(256) void range_kernel(RangeArgs A)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.count) return;
+    const uint32_t slot = A.first + i;
+    Tile tl{0u, 0u, 0u, 0u};
+    if (!A.clear) {
+        A.spec0[slot] = A.s0;
+        A.spec1[slot] = A.s1;
+        A.spec2[slot] = A.s2;
+        A.env_id[slot] = A.env_id_base + i;
+        for (int k = 0; k < 8; ++k) A.terr[8u * slot + (uint32_t)k] = A.terr_words[k];
+        const uint32_t E = 64u / A.lanes;  // envs per tile
+        if (i * E < A.count) {
+            tl.job = A.job_index;
+            tl.env0 = A.first + i * E;
+            tl.count = A.count - i * E < E ? A.count - i * E : E;
+            tl.variant = A.variant;
+        }
+        if (i == 0) {
+            A.jobs[A.job_index] = A.job;
+            A.job_err[A.job_index] = 0xffffffffu;
+        }
+    }
+    A.tiles[slot] = tl;
+}
+
+hipError_t launch_range(const RangeArgs &a, hipStream_t stream)
+{
+    if (a.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(range_kernel, dim3((a.count + 255) / 256), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

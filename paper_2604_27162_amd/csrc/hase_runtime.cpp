@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <list>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -123,7 +124,9 @@ int check_spec(const hase_env_spec &s, uint32_t idx)
 
 struct Regions {
     size_t perm, spec0, spec1, spec2, obs_off, agent_off, bb_off, grid_off, env_id, map_off, terr;
-    size_t seed, found, t, ep, steps, stuck, bel, pos, walls, bb, disc, tiles, err, total;
+    size_t seed, found, t, ep, steps, stuck, bel, pos, walls, bb, disc, tiles, err;
+    size_t jobs, job_err;  // arenas only: the ranges' job descriptors and error words
+    size_t total;
 };
 
 struct Plan {
@@ -228,7 +231,7 @@ constexpr int MAX_LAUNCHES = 5 * N_KINDS;
 
 struct GraphEntry {
     uint32_t n_steps;
-    const void *act, *obs, *rew, *done, *map;
+    const void *act, *obs, *rew, *done, *map, *spos, *senv;
     hipGraphExec_t exec;
 };
 
@@ -246,6 +249,16 @@ struct hase_batch {
     hipStream_t side[MAX_LAUNCHES] = {};
     hipEvent_t fork_ev = nullptr, join_ev[MAX_LAUNCHES] = {};
     std::list<GraphEntry> graphs;  // most recently used first
+
+    // arena (hase_create_arena): n_envs slots of capacity cap_h x cap_w
+    // cells and cap_n agents; ranges of slots admitted by hase_reset_range
+    struct Range {
+        uint32_t count, job, kind, lanes, n_tiles, slot_words, map_words;
+    };
+    bool arena = false;
+    uint32_t cap_h = 0, cap_w = 0, cap_n = 0;
+    std::map<uint32_t, Range> ranges;  // by first slot
+    std::vector<uint32_t> free_jobs;
 
     template <class T>
     T *at(size_t off) const { return reinterpret_cast<T *>(d + off); }
@@ -389,6 +402,11 @@ JobDesc make_job(const hase_batch *b, const int8_t *act, uint32_t *obs, float *r
     j.bel = b->at<uint32_t>(r.bel);
     j.map = map;
     j.map_stride = b->plan.map_words;
+    j.spos = nullptr;
+    j.senv = nullptr;
+    j.resident = 0;
+    j.first = j.budget = j.obs_env = j.map_env = 0;
+    j.group = ALL_GROUPS;
     return j;
 }
 
@@ -443,7 +461,8 @@ int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_
     if (rc) return rc;
     for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
         if (it->n_steps == n_steps && it->act == job.act && it->obs == job.obs &&
-            it->rew == job.rew && it->done == job.done && it->map == job.map) {
+            it->rew == job.rew && it->done == job.done && it->map == job.map &&
+            it->spos == job.spos && it->senv == job.senv) {
             b->graphs.splice(b->graphs.begin(), b->graphs, it);
             *out = b->graphs.front().exec;
             return HASE_OK;
@@ -464,7 +483,7 @@ int graph_for(hase_batch *b, const JobDesc &job, uint32_t n_steps, hipGraphExec_
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    GraphEntry g{n_steps, job.act, job.obs, job.rew, job.done, job.map, exec};
+    GraphEntry g{n_steps, job.act, job.obs, job.rew, job.done, job.map, job.spos, job.senv, exec};
     b->graphs.push_front(g);
     while (b->graphs.size() > 8) {
         (void)hipGraphExecDestroy(b->graphs.back().exec);
@@ -494,6 +513,7 @@ int check_step_args(const hase_batch *b, uint32_t n_steps, const uint32_t *d_obs
                     const uint8_t *d_done)
 {
     if (!b) return fail(HASE_EINVAL, "null handle");
+    if (b->arena) return fail(HASE_EINVAL, "an arena is stepped by hase_step_resident");
     if (!b->ready) return fail(HASE_ENOTREADY, "step before reset/set_state");
     if (n_steps == 0) return fail(HASE_EINVAL, "n_steps must be >= 1");
     if (!d_obs || !d_rew || !d_done) return fail(HASE_EINVAL, "null output buffer");
@@ -518,6 +538,7 @@ InitArgs make_init(const hase_batch *b, uint64_t seed, uint32_t rebuild)
     a.bel = b->at<uint32_t>(r.bel);
     a.err = b->at<uint32_t>(r.err);
     a.seed_value = seed;
+    a.env0 = 0;
     a.n_envs = b->n_envs;
     a.rebuild_only = rebuild;
     return a;
@@ -701,6 +722,7 @@ int hase_create(const hase_batch_desc *desc, void *d_state, uint64_t state_bytes
 
 int hase_get_offsets(const hase_batch *b, uint64_t *h_obs_off, uint64_t *h_agent_off)
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_get_offsets: not an operation of an arena");
     if (!b) return fail(HASE_EINVAL, "null handle");
     for (uint32_t e = 0; e < b->n_envs; ++e) {
         if (h_obs_off) h_obs_off[e] = b->plan.obs_off[e];
@@ -711,6 +733,7 @@ int hase_get_offsets(const hase_batch *b, uint64_t *h_obs_off, uint64_t *h_agent
 
 int hase_get_map_offsets(const hase_batch *b, uint64_t *h_map_off)
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_get_map_offsets: not an operation of an arena");
     if (!b || !h_map_off) return fail(HASE_EINVAL, "null argument");
     for (uint32_t e = 0; e < b->n_envs; ++e) h_map_off[e] = b->plan.map_off[e];
     return HASE_OK;
@@ -718,6 +741,7 @@ int hase_get_map_offsets(const hase_batch *b, uint64_t *h_map_off)
 
 int hase_reset(hase_batch *b, uint64_t seed, uint32_t *d_obs0)
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_reset: not an operation of an arena");
     if (!b) return fail(HASE_EINVAL, "null handle");
     HIP_TRY(hipMemsetAsync(b->d + b->plan.reg.err, 0xff, 4, b->stream));
     HIP_TRY(launch_init(make_init(b, seed, 0), b->stream));
@@ -747,11 +771,21 @@ int hase_step(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t
 int hase_step_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
                    float *d_rew, uint8_t *d_done, uint32_t *d_map, uint32_t mode)
 {
-    const int rc0 = check_step_args(b, n_steps, d_obs, d_rew, d_done);
+    const hase_outputs out{d_obs, d_rew, d_done, d_map, nullptr, nullptr};
+    return hase_step_outputs(b, n_steps, d_actions, &out, mode);
+}
+
+int hase_step_outputs(hase_batch *b, uint32_t n_steps, const int8_t *d_actions,
+                      const hase_outputs *out, uint32_t mode)
+{
+    if (!out) return fail(HASE_EINVAL, "null outputs");
+    const int rc0 = check_step_args(b, n_steps, out->obs, out->rew, out->done);
     if (rc0) return rc0;
     if (mode != HASE_STEP_PERSISTENT && mode != HASE_STEP_PER_LAUNCH)
         return fail(HASE_EINVAL, "unknown step mode %u", mode);
-    const JobDesc job = make_job(b, d_actions, d_obs, d_rew, d_done, d_map);
+    JobDesc job = make_job(b, d_actions, out->obs, out->rew, out->done, out->map);
+    job.spos = out->pos;
+    job.senv = out->env_state;
     if (mode == HASE_STEP_PERSISTENT) return persistent_step(b, job, n_steps);
     if (b->variants.size() > 1) {
         const int rc = ensure_streams(b, b->variants.size());
@@ -773,15 +807,27 @@ int hase_prepare(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint3
 int hase_prepare_maps(hase_batch *b, uint32_t n_steps, const int8_t *d_actions, uint32_t *d_obs,
                       float *d_rew, uint8_t *d_done, uint32_t *d_map)
 {
-    const int rc = check_step_args(b, n_steps, d_obs, d_rew, d_done);
+    const hase_outputs out{d_obs, d_rew, d_done, d_map, nullptr, nullptr};
+    return hase_prepare_outputs(b, n_steps, d_actions, &out);
+}
+
+int hase_prepare_outputs(hase_batch *b, uint32_t n_steps, const int8_t *d_actions,
+                         const hase_outputs *out)
+{
+    if (!out) return fail(HASE_EINVAL, "null outputs");
+    const int rc = check_step_args(b, n_steps, out->obs, out->rew, out->done);
     if (rc) return rc;
     if (b->variants.size() == 1) return HASE_OK;  // launched directly, no graph
+    JobDesc job = make_job(b, d_actions, out->obs, out->rew, out->done, out->map);
+    job.spos = out->pos;
+    job.senv = out->env_state;
     hipGraphExec_t exec = nullptr;
-    return graph_for(b, make_job(b, d_actions, d_obs, d_rew, d_done, d_map), n_steps, &exec);
+    return graph_for(b, job, n_steps, &exec);
 }
 
 int hase_observe(hase_batch *b, uint32_t *d_obs)
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_observe: not an operation of an arena");
     if (!b) return fail(HASE_EINVAL, "null handle");
     if (!b->ready) return fail(HASE_ENOTREADY, "observe before reset/set_state");
     if (!d_obs) return fail(HASE_EINVAL, "null obs buffer");
@@ -790,6 +836,7 @@ int hase_observe(hase_batch *b, uint32_t *d_obs)
 
 int hase_get_state(hase_batch *b, const hase_host_state *out)
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_get_state: not an operation of an arena");
     if (!b || !out) return fail(HASE_EINVAL, "null argument");
     if (!out->walls || !out->pos_x || !out->pos_y || !out->found || !out->t || !out->episode ||
         !out->steps || !out->seed)
@@ -821,6 +868,7 @@ int hase_get_state(hase_batch *b, const hase_host_state *out)
 
 int hase_set_state(hase_batch *b, const hase_host_state *in)
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_set_state: not an operation of an arena");
     if (!b || !in) return fail(HASE_EINVAL, "null argument");
     if (!in->walls || !in->pos_x || !in->pos_y || !in->found || !in->t || !in->episode ||
         !in->steps || !in->seed)
@@ -911,6 +959,7 @@ int hase_set_state(hase_batch *b, const hase_host_state *in)
 
 int hase_set_tiling(hase_batch *b, const uint32_t lanes[HASE_N_BUCKETS])
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_set_tiling: not an operation of an arena");
     if (!b || !lanes) return fail(HASE_EINVAL, "null argument");
     uint32_t next[N_BUCKETS], dflt[N_BUCKETS];
     default_lanes(b->plan.specs, dflt);
@@ -932,6 +981,7 @@ int hase_set_tiling(hase_batch *b, const uint32_t lanes[HASE_N_BUCKETS])
 
 int hase_get_tiling(const hase_batch *b, uint32_t lanes[HASE_N_BUCKETS])
 {
+    if (b && b->arena) return fail(HASE_EINVAL, "hase_get_tiling: not an operation of an arena");
     if (!b || !lanes) return fail(HASE_EINVAL, "null argument");
     for (int i = 0; i < N_BUCKETS; ++i) lanes[i] = b->lanes[i];
     return HASE_OK;
@@ -988,6 +1038,7 @@ int hase_multi_workspace(hase_batch *const *batches, uint32_t n, uint64_t *bytes
     size_t tiles = 0;
     for (uint32_t i = 0; i < n; ++i) {
         if (!batches[i]) return fail(HASE_EINVAL, "null handle %u", i);
+        if (batches[i]->arena) return fail(HASE_EINVAL, "handle %u is an arena", i);
         tiles += batches[i]->host_tiles.size();
     }
     *bytes = align256(sizeof(JobDesc) * (size_t)(n ? n : 1)) + align256(sizeof(Tile) * (tiles ? tiles : 1));
@@ -1094,6 +1145,331 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
         if (fork && gi > 0) {
             HIP_TRY(hipEventRecord(fb->join_ev[gi], s));
             HIP_TRY(hipStreamWaitEvent(st, fb->join_ev[gi], 0));
+        }
+    }
+    return HASE_OK;
+}
+
+// ---------------------------------------------------------------- arenas
+
+int hase_query_arena(const hase_arena_desc *desc, uint64_t *state_bytes)
+{
+    if (!desc || !state_bytes) return fail(HASE_EINVAL, "null argument");
+    const uint64_t N = desc->n_slots;
+    if (N == 0 || N >= (1u << 26)) return fail(HASE_EINVAL, "n_slots must be in 1..2^26-1");
+    if (desc->max_height < 2 || desc->max_height > MAX_SIDE || desc->max_width < 2 ||
+        desc->max_width > MAX_SIDE)
+        return fail(HASE_EINVAL, "max_height/max_width must be in 2..%d", MAX_SIDE);
+    if (desc->max_agents < 1 || desc->max_agents > MAX_AGENTS)
+        return fail(HASE_EINVAL, "max_agents must be in 1..%d", MAX_AGENTS);
+    if (desc->max_ranges < 1 || desc->max_ranges > 65536)
+        return fail(HASE_EINVAL, "max_ranges must be in 1..65536");
+    const uint64_t A = N * desc->max_agents, cells = N * desc->max_height * desc->max_width;
+    const uint64_t bbw = N * (uint64_t)board_words(desc->max_height, 2);
+    const uint64_t mw = N * (uint64_t)map_words(desc->max_height, desc->max_width);
+    if (A >= (1ull << 32) || cells >= (1ull << 32) || bbw >= (1ull << 32))
+        return fail(HASE_EINVAL, "arena too large: offsets exceed 32 bits");
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    // the same regions as a batch (slot-indexed), plus the ranges' jobs
+    for (int i = 0; i < 10; ++i) take(4 * N);  // perm .. map_off
+    take(32 * N);                             // terr
+    take(8 * N);                              // seed
+    for (int i = 0; i < 5; ++i) take(4 * N);  // found, t, ep, steps, stuck
+    take(4 * A);                              // bel
+    take(2 * A);                              // pos
+    take(cells);                              // walls
+    take(4 * bbw);                            // bb
+    take(4 * mw);                             // disc
+    take(sizeof(Tile) * N);                   // tiles: tile i of a range at its slot first + i
+    take(16);                                 // err
+    take(sizeof(JobDesc) * desc->max_ranges); // jobs
+    take(4ull * desc->max_ranges);            // job_err
+    *state_bytes = off;
+    return HASE_OK;
+}
+
+int hase_create_arena(const hase_arena_desc *desc, void *d_state, uint64_t state_bytes, void *stream,
+                      hase_batch **out)
+{
+    if (!out) return fail(HASE_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    uint64_t need = 0;
+    int rc = hase_query_arena(desc, &need);
+    if (rc) return rc;
+    if (!d_state || ((uintptr_t)d_state & 255u))
+        return fail(HASE_EINVAL, "state buffer must be a non-null 256-byte aligned device pointer");
+    if (state_bytes < need)
+        return fail(HASE_ENOMEM, "state buffer has %llu bytes, needs %llu",
+                    (unsigned long long)state_bytes, (unsigned long long)need);
+    hase_batch *b = new hase_batch();
+    b->arena = true;
+    b->n_envs = desc->n_slots;
+    b->cap_h = desc->max_height;
+    b->cap_w = desc->max_width;
+    b->cap_n = desc->max_agents;
+    b->d = static_cast<char *>(d_state);
+    b->stream = static_cast<hipStream_t>(stream);
+    for (uint32_t j = desc->max_ranges; j-- > 0;) b->free_jobs.push_back(j);
+    const uint64_t N = desc->n_slots;
+    Regions &r = b->plan.reg;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const uint64_t A = N * b->cap_n;
+    const uint32_t bw = (uint32_t)board_words(b->cap_h, 2), mw = (uint32_t)map_words(b->cap_h, b->cap_w);
+    r.perm = take(4 * N);
+    r.spec0 = take(4 * N);
+    r.spec1 = take(4 * N);
+    r.spec2 = take(4 * N);
+    r.obs_off = take(4 * N);
+    r.agent_off = take(4 * N);
+    r.bb_off = take(4 * N);
+    r.grid_off = take(4 * N);
+    r.env_id = take(4 * N);
+    r.map_off = take(4 * N);
+    r.terr = take(32 * N);
+    r.seed = take(8 * N);
+    r.found = take(4 * N);
+    r.t = take(4 * N);
+    r.ep = take(4 * N);
+    r.steps = take(4 * N);
+    r.stuck = take(4 * N);
+    r.bel = take(4 * A);
+    r.pos = take(2 * A);
+    r.walls = take(N * b->cap_h * b->cap_w);
+    r.bb = take(4 * N * bw);
+    r.disc = take(4 * N * mw);
+    r.tiles = take(sizeof(Tile) * N);
+    r.err = take(16);
+    r.jobs = take(sizeof(JobDesc) * desc->max_ranges);
+    r.job_err = take(4ull * desc->max_ranges);
+    r.total = off;
+    // slot-indexed state offsets (every slot has the capacity of the caps);
+    // the tile table starts empty
+    std::vector<uint32_t> perm(N), zero(N, 0u), aoff(N), bboff(N), goff(N), moff(N);
+    for (uint32_t e = 0; e < N; ++e) {
+        perm[e] = e;
+        aoff[e] = e * b->cap_n;
+        bboff[e] = e * bw;
+        goff[e] = e * b->cap_h * b->cap_w;
+        moff[e] = e * mw;
+    }
+    std::vector<Tile> tiles(N, Tile{0u, 0u, 0u, 0u});
+    auto up = [&](size_t o, const void *src, size_t bytes) {
+        return hipMemcpyAsync(b->d + o, src, bytes, hipMemcpyHostToDevice, b->stream);
+    };
+    hipError_t e;
+    if ((e = up(r.perm, perm.data(), 4 * N)) != hipSuccess ||
+        (e = up(r.obs_off, zero.data(), 4 * N)) != hipSuccess ||
+        (e = up(r.agent_off, aoff.data(), 4 * N)) != hipSuccess ||
+        (e = up(r.bb_off, bboff.data(), 4 * N)) != hipSuccess ||
+        (e = up(r.grid_off, goff.data(), 4 * N)) != hipSuccess ||
+        (e = up(r.map_off, moff.data(), 4 * N)) != hipSuccess ||
+        (e = up(r.tiles, tiles.data(), sizeof(Tile) * N)) != hipSuccess ||
+        (e = hipStreamSynchronize(b->stream)) != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hase_create_arena upload");
+    }
+    b->ready = true;
+    *out = b;
+    return HASE_OK;
+}
+
+int hase_reset_range(hase_batch *b, uint32_t first_slot, uint32_t count, const hase_env_spec *spec,
+                     uint64_t seed, uint32_t env_id_base, uint32_t step_budget,
+                     const hase_out_ptrs *out)
+{
+    if (!b || !spec || !out) return fail(HASE_EINVAL, "null argument");
+    if (!b->arena) return fail(HASE_EINVAL, "hase_reset_range needs an arena (hase_create_arena)");
+    int rc = check_spec(*spec, 0);
+    if (rc) return rc;
+    const hase_env_spec &s = *spec;
+    if (s.height > b->cap_h || s.width > b->cap_w || s.n_agents > b->cap_n)
+        return fail(HASE_EINVAL, "spec %ux%u with %u agents exceeds the arena's %ux%u, %u agents",
+                    s.height, s.width, s.n_agents, b->cap_h, b->cap_w, b->cap_n);
+    if (count == 0 || (uint64_t)first_slot + count > b->n_envs)
+        return fail(HASE_EINVAL, "slots [%u, %u + %u) outside the arena's %u", first_slot, first_slot,
+                    count, b->n_envs);
+    if (step_budget == 0) return fail(HASE_EINVAL, "step_budget must be >= 1");
+    if (!out->obs || !out->rew || !out->done) return fail(HASE_EINVAL, "null output buffer");
+    // no overlap with an admitted range
+    auto nx = b->ranges.lower_bound(first_slot);
+    if (nx != b->ranges.end() && nx->first < first_slot + count)
+        return fail(HASE_EINVAL, "slots from %u are taken by the range at %u", first_slot, nx->first);
+    if (nx != b->ranges.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second.count > first_slot)
+            return fail(HASE_EINVAL, "slot %u is taken by the range at %u", first_slot, pv->first);
+    }
+    if (b->free_jobs.empty()) return fail(HASE_EINVAL, "the arena holds its maximum of ranges");
+    // tiling: the default lanes of the spec's bucket, widened while the
+    // wave's LDS (envs per wave x cap-sized slot) would exceed 64 KiB
+    const int kind = env_kind(s.flags);
+    const int planes = (s.flags & HASE_TERRAIN) ? 2 : 1;
+    const uint32_t slot_words = (uint32_t)board_words((int)b->cap_h, planes);
+    const uint32_t mwl = (s.flags & HASE_EXPLORE) ? (uint32_t)round4(lds_board_words((int)b->cap_h)) : 0u;
+    const int bk = bucket_of(s.n_agents);
+    uint32_t lanes = DEFAULT_LANES[bk];
+    while (lanes < 16 && (size_t)(64u / lanes) * (slot_words + MAX_AGENTS + mwl) * 4 > 65536) lanes *= 2;
+    if (!variant_supported((int)lanes, BUCKET_NMAX[bk]) ||
+        (size_t)(64u / lanes) * (slot_words + MAX_AGENTS + mwl) * 4 > 65536)
+        return fail(HASE_EINVAL, "no tiling fits this spec in LDS");
+    const uint32_t E = 64u / lanes;
+    const uint32_t w = (uint32_t)words_per_channel(s.view_radius);
+    const uint32_t obs_env = s.n_agents * (s.n_channels * w + ((s.flags & HASE_RADIO) ? 1u : 0u));
+    const uint32_t map_env = (s.flags & HASE_EXPLORE) ? (uint32_t)map_words(s.height, s.width) : 0u;
+    if ((uint64_t)count * obs_env >= (1ull << 32) || (uint64_t)count * s.n_agents >= (1ull << 32))
+        return fail(HASE_EINVAL, "range too large: per-step output offsets exceed 32 bits");
+
+    const uint32_t job = b->free_jobs.back();
+    const Regions &r = b->plan.reg;
+    JobDesc j = make_job(b, nullptr, out->obs, out->rew, out->done, out->map);
+    j.spos = out->pos;
+    j.senv = out->env_state;
+    j.obs_stride = (uint64_t)count * obs_env;
+    j.agent_stride = (uint64_t)count * s.n_agents;
+    j.env_stride = count;
+    j.map_stride = (uint64_t)count * map_env;
+    j.resident = 1;
+    j.first = first_slot;
+    j.budget = step_budget;
+    j.obs_env = obs_env;
+    j.map_env = map_env;
+
+    RangeArgs a{};
+    a.spec0 = b->at<uint32_t>(r.spec0);
+    a.spec1 = b->at<uint32_t>(r.spec1);
+    a.spec2 = b->at<uint32_t>(r.spec2);
+    a.terr = b->at<uint32_t>(r.terr);
+    a.env_id = b->at<uint32_t>(r.env_id);
+    a.tiles = b->at<Tile>(r.tiles);
+    a.jobs = b->at<JobDesc>(r.jobs);
+    a.job_err = b->at<uint32_t>(r.job_err);
+    a.job = j;
+    a.job_index = job;
+    a.first = first_slot;
+    a.count = count;
+    a.clear = 0;
+    a.s0 = s.height | (s.width << 8) | ((uint32_t)s.n_agents << 16) | ((uint32_t)s.n_seekers << 24);
+    a.s1 = s.view_radius | ((uint32_t)s.n_channels << 4) | ((uint32_t)s.flags << 8) |
+           ((uint32_t)s.episode_len << 16);
+    a.s2 = s.wall_pct | ((uint32_t)board_words_per_row(s.width) << 8);
+    a.env_id_base = env_id_base;
+    a.lanes = lanes;
+    a.variant = (uint32_t)(bk * 4 + s.view_radius - 1) | (group_code(kind, (int)lanes) << 8);
+    if (s.flags & HASE_TERRAIN) {
+        a.terr_words[0] = s.water_pct | ((uint32_t)s.mud_pct << 8) | ((uint32_t)s.stuck_pct << 16);
+        for (int k = 0; k < 9; ++k) a.terr_words[1 + k / 4] |= (uint32_t)s.speed_pct[k] << (8 * (k % 4));
+        a.terr_words[4] = (uint32_t)s.agent_classes;
+        a.terr_words[5] = (uint32_t)(s.agent_classes >> 32);
+    }
+    HIP_TRY(launch_range(a, b->stream));
+    InitArgs ia = make_init(b, seed, 0);
+    ia.err = b->at<uint32_t>(r.job_err) + job;
+    ia.env0 = first_slot;
+    ia.n_envs = count;
+    HIP_TRY(launch_init(ia, b->stream));
+    if (out->err)
+        HIP_TRY(hipMemcpyAsync(out->err, ia.err, 4, hipMemcpyDefault, b->stream));
+    const uint32_t n_tiles = (count + E - 1) / E;
+    if (out->obs0) {
+        // the first observation: an observe-only launch over the range's tiles
+        JobDesc j0 = j;
+        j0.obs = out->obs0;
+        j0.obs_stride = 0;
+        HIP_TRY(launch_mixed((int)lanes, kind, b->at<Tile>(r.tiles) + first_slot, n_tiles, nullptr, j0,
+                             0, 0, slot_words, mwl, b->stream));
+    }
+    b->free_jobs.pop_back();
+    b->ranges[first_slot] = hase_batch::Range{count, job, (uint32_t)kind, lanes, n_tiles, slot_words, mwl};
+    return HASE_OK;
+}
+
+int hase_release_range(hase_batch *b, uint32_t first_slot)
+{
+    if (!b) return fail(HASE_EINVAL, "null handle");
+    if (!b->arena) return fail(HASE_EINVAL, "hase_release_range needs an arena");
+    auto it = b->ranges.find(first_slot);
+    if (it == b->ranges.end()) return fail(HASE_EINVAL, "no range starts at slot %u", first_slot);
+    RangeArgs a{};
+    a.tiles = b->at<Tile>(b->plan.reg.tiles);
+    a.first = first_slot;
+    a.count = it->second.count;
+    a.clear = 1;
+    HIP_TRY(launch_range(a, b->stream));
+    b->free_jobs.push_back(it->second.job);
+    b->ranges.erase(it);
+    return HASE_OK;
+}
+
+int hase_range_error(hase_batch *b, uint32_t first_slot, int64_t *bad_env)
+{
+    if (!b || !bad_env) return fail(HASE_EINVAL, "null argument");
+    if (!b->arena) return fail(HASE_EINVAL, "hase_range_error needs an arena");
+    auto it = b->ranges.find(first_slot);
+    if (it == b->ranges.end()) return fail(HASE_EINVAL, "no range starts at slot %u", first_slot);
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, b->d + b->plan.reg.job_err + 4ull * it->second.job, 4,
+                           hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    *bad_env = err == 0xffffffffu ? -1 : (int64_t)err;
+    return HASE_OK;
+}
+
+int hase_step_resident(hase_batch *b, uint32_t n_steps)
+{
+    if (!b) return fail(HASE_EINVAL, "null handle");
+    if (!b->arena) return fail(HASE_EINVAL, "hase_step_resident needs an arena");
+    if (n_steps == 0) return fail(HASE_EINVAL, "n_steps must be >= 1");
+    // one launch per (kind, lanes) group over the tile entries up to the
+    // group's last range (a wave skips entries of other groups and empty
+    // ones); groups run concurrently on forked streams
+    struct G {
+        uint32_t kind, lanes, extent, slot, map;
+    };
+    std::vector<G> groups;
+    for (const auto &kv : b->ranges) {
+        const hase_batch::Range &rg = kv.second;
+        G *g = nullptr;
+        for (G &x : groups)
+            if (x.kind == rg.kind && x.lanes == rg.lanes) g = &x;
+        if (!g) {
+            groups.push_back(G{rg.kind, rg.lanes, 0u, rg.slot_words, rg.map_words});
+            g = &groups.back();
+        }
+        g->extent = std::max(g->extent, kv.first + rg.n_tiles);
+    }
+    if (groups.empty()) return HASE_OK;
+    const bool fork = groups.size() > 1;
+    if (fork) {
+        const int rc = ensure_streams(b, groups.size());
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b->fork_ev, b->stream));
+    }
+    const Tile *tiles = b->at<Tile>(b->plan.reg.tiles);
+    const JobDesc *jobs = b->at<JobDesc>(b->plan.reg.jobs);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const G &g = groups[gi];
+        JobDesc filter{};
+        filter.group = group_code((int)g.kind, (int)g.lanes);
+        hipStream_t st = b->stream;
+        if (fork && gi > 0) {
+            HIP_TRY(hipStreamWaitEvent(b->side[gi], b->fork_ev, 0));
+            st = b->side[gi];
+        }
+        HIP_TRY(launch_mixed((int)g.lanes, (int)g.kind, tiles, g.extent, jobs, filter, n_steps, 0,
+                             g.slot, g.map, st));
+        if (fork && gi > 0) {
+            HIP_TRY(hipEventRecord(b->join_ev[gi], st));
+            HIP_TRY(hipStreamWaitEvent(b->stream, b->join_ev[gi], 0));
         }
     }
     return HASE_OK;

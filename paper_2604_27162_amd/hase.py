@@ -60,6 +60,23 @@ class HostState(ctypes.Structure):
                 ("stuck", ctypes.c_void_p), ("belief", ctypes.c_void_p)]
 
 
+class ArenaDesc(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_uint32), ("max_height", ctypes.c_uint16),
+                ("max_width", ctypes.c_uint16), ("max_agents", ctypes.c_uint8),
+                ("max_ranges", ctypes.c_uint32)]
+
+
+class OutPtrs(ctypes.Structure):
+    _fields_ = [("obs", ctypes.c_void_p), ("rew", ctypes.c_void_p), ("done", ctypes.c_void_p),
+                ("map", ctypes.c_void_p), ("obs0", ctypes.c_void_p), ("err", ctypes.c_void_p),
+                ("pos", ctypes.c_void_p), ("env_state", ctypes.c_void_p)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("obs", ctypes.c_void_p), ("rew", ctypes.c_void_p), ("done", ctypes.c_void_p),
+                ("map", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("env_state", ctypes.c_void_p)]
+
+
 class StepIO(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_void_p), ("n_steps", ctypes.c_uint32),
                 ("out_step0", ctypes.c_uint32), ("d_actions", ctypes.c_void_p),
@@ -71,7 +88,10 @@ EXPORTS = ("hase_query_layout", "hase_create", "hase_get_offsets", "hase_get_map
            "hase_reset", "hase_step", "hase_step_maps", "hase_prepare", "hase_prepare_maps",
            "hase_observe", "hase_get_state", "hase_set_state", "hase_set_tiling",
            "hase_get_tiling", "hase_autotune", "hase_multi_workspace", "hase_step_multi",
-           "hase_step_multi_static", "hase_destroy", "hase_strerror", "hase_last_error")
+           "hase_step_multi_static", "hase_step_outputs", "hase_prepare_outputs",
+           "hase_query_arena", "hase_create_arena",
+           "hase_reset_range", "hase_step_resident", "hase_release_range", "hase_range_error",
+           "hase_destroy", "hase_strerror", "hase_last_error")
 STATIC_WORKSPACE_BYTES = 1 << 20
 
 _lib = None
@@ -84,6 +104,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with python -m paper_2604_27162_amd.build")
+    try:
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so both see the same devices, streams and memory
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
     sig = {
@@ -105,6 +131,15 @@ def load(path: str = LIB_PATH):
         "hase_multi_workspace": [ctypes.POINTER(vp), u32, ctypes.POINTER(u64)],
         "hase_step_multi": [ctypes.POINTER(StepIO), u32, u32, vp, u64, vp],
         "hase_step_multi_static": [ctypes.POINTER(StepIO), u32, u32, vp],
+        "hase_step_outputs": [vp, u32, vp, ctypes.POINTER(Outputs), u32],
+        "hase_prepare_outputs": [vp, u32, vp, ctypes.POINTER(Outputs)],
+        "hase_query_arena": [ctypes.POINTER(ArenaDesc), ctypes.POINTER(u64)],
+        "hase_create_arena": [ctypes.POINTER(ArenaDesc), vp, u64, vp, ctypes.POINTER(vp)],
+        "hase_reset_range": [vp, u32, u32, ctypes.POINTER(EnvSpec), u64, u32, u32,
+                             ctypes.POINTER(OutPtrs)],
+        "hase_step_resident": [vp, u32],
+        "hase_release_range": [vp, u32],
+        "hase_range_error": [vp, u32, ctypes.POINTER(ctypes.c_int64)],
         "hase_destroy": [vp],
         "hase_strerror": [ctypes.c_int],
         "hase_last_error": [],
@@ -195,6 +230,14 @@ class HaseBatch:
             return obs, rew, done, mp
         return obs, rew, done
 
+    def alloc_state_outputs(self, n_steps: int):
+        """(pos, env_state) tensors of the true state after each of n_steps:
+        int16 [n_steps][agents] (x | y << 8) and int32 [n_steps][envs][4]
+        (found, t, episode, stuck)."""
+        t = self.torch
+        return (t.empty((n_steps, self.agents), dtype=t.int16, device=self.device),
+                t.empty((n_steps, self.n_envs, 4), dtype=t.int32, device=self.device))
+
     def reset(self, seed: int, obs: bool = True):
         """reset(seed); returns the first observation (None with obs=False:
         then no observation is written)."""
@@ -213,10 +256,22 @@ class HaseBatch:
             raise ValueError("map tensor has the wrong device, layout or size")
         return maps.data_ptr()
 
+    def _state_ptrs(self, state, n_steps: int):
+        if state is None:
+            return None, None
+        pos, env = state
+        if (pos.device != self.device or not pos.is_contiguous() or pos.element_size() != 2
+                or pos.numel() < n_steps * self.agents or env.device != self.device
+                or not env.is_contiguous() or env.element_size() != 4
+                or env.numel() < n_steps * self.n_envs * 4):
+            raise ValueError("true-state tensors have the wrong device, layout or size")
+        return pos.data_ptr(), env.data_ptr()
+
     def step_into(self, obs, rew, done, n_steps: int, actions=None, mode: int = PERSISTENT,
-                  maps=None):
+                  maps=None, state=None):
         """Enqueue n_steps into preallocated outputs (no synchronisation);
-        maps (optional) receives the discovery maps after every step."""
+        maps (optional) receives the discovery maps after every step, state
+        (optional, alloc_state_outputs) the true state after every step."""
         for tns, shape in ((obs, (n_steps, self.obs_words)), (rew, (n_steps, self.agents)),
                            (done, (n_steps, self.n_envs))):
             if tns.device != self.device or not tns.is_contiguous() or tns.numel() < shape[0] * shape[1]:
@@ -229,25 +284,33 @@ class HaseBatch:
                 raise ValueError("actions must be a contiguous int8 device tensor "
                                  "[n_steps][agents_total]")
             aptr = actions.data_ptr()
-        _check(load().hase_step_maps(self._h, int(n_steps), aptr, obs.data_ptr(), rew.data_ptr(),
-                                     done.data_ptr(), mptr, int(mode)))
+        pp, ep = self._state_ptrs(state, n_steps)
+        outs = Outputs(obs.data_ptr(), rew.data_ptr(), done.data_ptr(), mptr, pp, ep)
+        _check(load().hase_step_outputs(self._h, int(n_steps), aptr, ctypes.byref(outs), int(mode)))
 
-    def prepare(self, obs, rew, done, n_steps: int, actions=None, maps=None) -> None:
+    def prepare(self, obs, rew, done, n_steps: int, actions=None, maps=None, state=None) -> None:
         """Capture the persistent-step graph for these buffers without running it."""
         aptr = None if actions is None else actions.data_ptr()
-        _check(load().hase_prepare_maps(self._h, int(n_steps), aptr, obs.data_ptr(),
-                                        rew.data_ptr(), done.data_ptr(),
-                                        self._map_ptr(maps, n_steps)))
+        pp, ep = self._state_ptrs(state, n_steps)
+        outs = Outputs(obs.data_ptr(), rew.data_ptr(), done.data_ptr(),
+                       self._map_ptr(maps, n_steps), pp, ep)
+        _check(load().hase_prepare_outputs(self._h, int(n_steps), aptr, ctypes.byref(outs)))
 
-    def step(self, n_steps: int = 1, actions=None, mode: int = PERSISTENT, maps: bool = False):
-        """(obs, rew, done) of n_steps, plus the discovery maps when maps."""
+    def step(self, n_steps: int = 1, actions=None, mode: int = PERSISTENT, maps: bool = False,
+             state: bool = False):
+        """(obs, rew, done) of n_steps, plus the discovery maps when maps, plus
+        the true state (pos, env_state) after every step when state."""
         out = self.alloc_outputs(n_steps, maps)
+        st = self.alloc_state_outputs(n_steps) if state else None
         if actions is not None and not self.torch.is_tensor(actions):
             actions = self.torch.as_tensor(np.ascontiguousarray(actions, np.int8)).to(self.device)
-        self.step_into(*out[:3], n_steps, actions, mode, out[3] if maps else None)
+        self.step_into(*out[:3], n_steps, actions, mode, out[3] if maps else None, st)
+        res = tuple(out[:3])
         if maps:
-            return out[0], out[1], out[2], out[3][:, :self.map_words]
-        return out
+            res += (out[3][:, :self.map_words],)
+        if state:
+            res += st
+        return res
 
     def observe(self):
         obs = self.torch.empty(self.obs_words, dtype=self.torch.int32, device=self.device)
@@ -388,3 +451,123 @@ def step_multi_static(items, n_steps: int, stream) -> None:
     _check(load().hase_step_multi_static(_step_ios(items), len(items), int(n_steps),
                                          ctypes.c_void_p(stream.cuda_stream)))
 
+
+def range_output_sizes(spec: dict, count: int) -> dict:
+    """Per-step output sizes (elements) of a range of `count` envs of spec."""
+    d = 2 * spec["r"] + 1
+    w = (d * d + 31) // 32
+    obs_env = spec["n"] * (spec["C"] * w + (1 if spec["flags"] & RADIO else 0))
+    map_env = spec["H"] * ((spec["W"] + 31) // 32) if spec["flags"] & EXPLORE else 0
+    return dict(obs=count * obs_env, rew=count * spec["n"], done=count, map=count * map_env)
+
+
+def query_arena(n_slots: int, max_height: int = 64, max_width: int = 64, max_agents: int = 20,
+                max_ranges: int = 1024) -> int:
+    d = ArenaDesc(n_slots, max_height, max_width, max_agents, max_ranges)
+    out = ctypes.c_uint64()
+    _check(load().hase_query_arena(ctypes.byref(d), ctypes.byref(out)))
+    return int(out.value)
+
+
+class HaseArena:
+    """Resident env slots on one device (include/hase.h, arena): ranges of
+    slots are admitted with their own spec, seed, env ids, step budget and
+    output tensors, stepped together, and released."""
+
+    def __init__(self, n_slots: int, max_height: int = 64, max_width: int = 64,
+                 max_agents: int = 20, max_ranges: int = 1024, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        L = load()
+        self.device = torch.device(device)
+        self.desc = ArenaDesc(n_slots, max_height, max_width, max_agents, max_ranges)
+        nbytes = ctypes.c_uint64()
+        _check(L.hase_query_arena(ctypes.byref(self.desc), ctypes.byref(nbytes)))
+        self.state_bytes = int(nbytes.value)
+        self.state = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+        if self.state.data_ptr() % 256:
+            raise RuntimeError("state buffer not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(L.hase_create_arena(ctypes.byref(self.desc), self.state.data_ptr(), nbytes,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.n_slots = int(n_slots)
+
+    def alloc_outputs(self, spec: dict, count: int, steps: int, maps: bool = False,
+                      state: bool = False):
+        """(obs, rew, done[, map][, pos, env_state]) tensors of a range, plus
+        obs0 and a pinned host error word, laid out as hase_out_ptrs
+        describes."""
+        t = self.torch
+        sz = range_output_sizes(spec, count)
+        out = dict(obs=t.empty((steps, sz["obs"]), dtype=t.int32, device=self.device),
+                   rew=t.empty((steps, sz["rew"]), dtype=t.float32, device=self.device),
+                   done=t.empty((steps, sz["done"]), dtype=t.uint8, device=self.device),
+                   obs0=t.empty(sz["obs"], dtype=t.int32, device=self.device),
+                   err=t.full((1,), -2, dtype=t.int32, pin_memory=True))
+        if maps and sz["map"]:
+            out["map"] = t.empty((steps, sz["map"]), dtype=t.int32, device=self.device)
+        if state:
+            out["pos"] = t.empty((steps, sz["rew"]), dtype=t.int16, device=self.device)
+            out["env_state"] = t.empty((steps, count, 4), dtype=t.int32, device=self.device)
+        return out
+
+    def reset_range(self, first_slot: int, count: int, spec: dict, seed: int, steps: int,
+                    out: dict, env_id_base: int = 0) -> None:
+        """Admit `count` envs of spec at first_slot (enqueued): out holds the
+        range's tensors (alloc_outputs; "map" and "obs0" optional)."""
+        sz = range_output_sizes(spec, count)
+        for k in ("obs", "rew", "done"):
+            x = out[k]
+            if (x.device != self.device or not x.is_contiguous()
+                    or x.numel() < steps * sz[k]):
+                raise ValueError(f"output tensor {k} has the wrong device, layout or size")
+        mp, o0, er = out.get("map"), out.get("obs0"), out.get("err")
+        if mp is not None and (not mp.is_contiguous() or mp.numel() < steps * sz["map"]):
+            raise ValueError("map tensor has the wrong layout or size")
+        if o0 is not None and (not o0.is_contiguous() or o0.numel() < sz["obs"]):
+            raise ValueError("obs0 tensor has the wrong layout or size")
+        if er is not None and (er.element_size() * er.numel() < 4
+                               or not (er.is_cuda or er.is_pinned())):
+            raise ValueError("err must be a device or pinned host tensor of one 32-bit word")
+        sp_, se_ = out.get("pos"), out.get("env_state")
+        if sp_ is not None and (not sp_.is_contiguous() or sp_.element_size() != 2
+                                or sp_.numel() < steps * sz["rew"]):
+            raise ValueError("pos tensor has the wrong layout or size")
+        if se_ is not None and (not se_.is_contiguous() or se_.element_size() != 4
+                                or se_.numel() < steps * 4 * count):
+            raise ValueError("env_state tensor has the wrong layout or size")
+        ptrs = OutPtrs(out["obs"].data_ptr(), out["rew"].data_ptr(), out["done"].data_ptr(),
+                       None if mp is None else mp.data_ptr(), None if o0 is None else o0.data_ptr(),
+                       None if er is None else er.data_ptr(),
+                       None if sp_ is None else sp_.data_ptr(), None if se_ is None else se_.data_ptr())
+        sp = spec_struct(spec)
+        _check(load().hase_reset_range(self._h, int(first_slot), int(count), ctypes.byref(sp),
+                                       ctypes.c_uint64(seed), int(env_id_base), int(steps),
+                                       ctypes.byref(ptrs)))
+
+    def step(self, n_steps: int) -> None:
+        _check(load().hase_step_resident(self._h, int(n_steps)))
+
+    def release_range(self, first_slot: int) -> None:
+        _check(load().hase_release_range(self._h, int(first_slot)))
+
+    def range_error(self, first_slot: int) -> int:
+        """-1, or the first env of the range without room for its agents
+        (synchronises)."""
+        v = ctypes.c_int64()
+        _check(load().hase_range_error(self._h, int(first_slot), ctypes.byref(v)))
+        return int(v.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hase_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -96,3 +96,22 @@ def test_null_handles(lib):
 def test_error_strings(lib):
     for code in (0, -1, -2, -3, -4, -5, -6, -99):
         assert lib.hase_strerror(code)
+
+
+def test_arena_query_validates(lib):
+    assert hase.query_arena(1000, 64, 64, 10, 64) % 256 == 0
+    small = hase.query_arena(1000, 16, 16, 2, 64)
+    assert small < hase.query_arena(1000, 64, 64, 10, 64)
+    for bad in (dict(n_slots=0), dict(max_height=1), dict(max_width=65), dict(max_agents=0),
+                dict(max_agents=21), dict(max_ranges=0)):
+        kw = dict(n_slots=10, max_height=16, max_width=16, max_agents=4, max_ranges=4)
+        kw.update(bad)
+        with pytest.raises(hase.HaseError) as ei:
+            hase.query_arena(**kw)
+        assert ei.value.code == hase.EINVAL
+
+
+def test_arena_calls_reject_null_handles(lib):
+    assert lib.hase_step_resident(None, 1) == hase.EINVAL
+    assert lib.hase_release_range(None, 0) == hase.EINVAL
+    assert lib.hase_reset_range(None, 0, 1, None, 1, 0, 1, None) == hase.EINVAL

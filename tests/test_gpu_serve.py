@@ -56,10 +56,14 @@ def test_step_multi_matches_separate_batches():
 
 
 def test_server_alone_vs_mix_bit_exact():
-    trace = wl.serving_trace(8, rate_per_s=1e6, seed=21)
+    """Requests served together in the arena, some admitted while others
+    run and into slots others left, equal the same requests run alone and
+    the oracle (obs, rewards as float32 bits, dones) for every request."""
+    trace = wl.serving_trace(10, rate_per_s=1e6, seed=21)
     reqs = [serve.Request(t["rid"], t["spec"], t["n_envs"] // 8, t["steps"] // 4, t["seed"])
             for t in trace]
-    srv = serve.Server(serve.HipExecutor(DEV), budget_bytes=64 << 30, chunk=32)
+    ex = serve.HipExecutor(DEV, n_slots=1200, max_ranges=6)
+    srv = serve.Server(ex, budget_bytes=64 << 30, chunk=32)
     for r in reqs[:4]:
         srv.submit(r)
     srv.step_once()
@@ -67,36 +71,44 @@ def test_server_alone_vs_mix_bit_exact():
     for r in reqs[4:]:
         srv.submit(r)
     srv.drain()
-    st = srv.stats()
+    while srv.inflight:
+        srv.step_once()
+    st = srv.stats(1.0)
     assert st["requests_done"] == len(reqs)
+    slots = [r.first_slot for r in reqs]
+    assert len(set(slots)) < len(slots)  # some slots were taken twice
     for r in reqs:
         got = srv.fetch(r)
+        assert r.outputs is None
         want = alone(r.spec, r.n_envs, r.seed, r.steps)
         for g, w in zip(got, want):
             assert torch.equal(g, w), r.rid
-    # and one request against the oracle
-    r = reqs[0]
-    ob = o.OracleBatch([r.spec] * r.n_envs)
-    ob.reset(r.seed)
-    oo, orr, od = ob.step(r.steps)
-    go, gr, gd = r.outputs
-    assert np.array_equal(go.cpu().numpy().view(np.uint32), oo)
-    assert np.array_equal(gd.cpu().numpy(), od)
-    assert srv.used == 0
+        ob = o.OracleBatch([r.spec] * r.n_envs)
+        ob.reset(r.seed)
+        oo, orr, od = ob.step(r.steps)
+        go, gr, gd = got
+        assert np.array_equal(go.cpu().numpy().view(np.uint32), oo), r.rid
+        assert np.array_equal(gr.cpu().numpy().view(np.uint32), orr.view(np.uint32)), r.rid
+        assert np.array_equal(gd.cpu().numpy(), od), r.rid
+    assert srv.used == ex.fixed_bytes
 
 
 def test_server_budget_queues_until_fetch():
     trace = wl.serving_trace(3, rate_per_s=1e6, seed=22)
     reqs = [serve.Request(t["rid"], t["spec"], 64, 40, t["seed"]) for t in trace]
-    ex = serve.HipExecutor(DEV)
+    ex = serve.HipExecutor(DEV, n_slots=512, max_ranges=8)
     fp = [ex.footprint(r) for r in reqs]
-    srv = serve.Server(ex, budget_bytes=max(fp), chunk=64)
+    srv = serve.Server(ex, budget_bytes=max(fp) + ex.fixed_bytes, chunk=64)
     for r in reqs:
         srv.submit(r)
     srv.step_once()
+    while srv.inflight:
+        srv.step_once()
     assert reqs[0].state == "done" and reqs[1].state == "queued"
     srv.fetch(reqs[0])
     srv.step_once()
+    while srv.inflight:
+        srv.step_once()
     assert reqs[1].state == "done"
 
 

@@ -1,5 +1,8 @@
-"""Serving-loop scheduling on the CPU, with a test-double executor that runs
-requests on the oracle (the product executor runs them on the GPU)."""
+"""Serving-loop scheduling on the CPU, with a test-double executor that keeps
+each admitted request as an oracle batch (the product executor keeps them in
+a device arena). Covers slot and budget admission, chunking with each
+request's own budget, release and slot reuse, fetch handing outputs over,
+failure isolation and the background loop."""
 import threading
 
 import numpy as np
@@ -9,54 +12,87 @@ from oracle import oracle as o
 from paper_2604_27162_amd import serve, workloads as wl
 
 
-class OracleExecutor:
-    """Executor test double: every request is an oracle batch."""
+class Ev:
+    """Stand-in for a device event: complete at once, no duration."""
 
-    def __init__(self, fail_rids=()):
-        self.fail_rids = set(fail_rids)
-        self.created = []
+    def query(self):
+        return True
+
+
+class OracleArenaExecutor:
+    """Executor test double: an arena of n_slots whose admitted ranges are
+    oracle batches, stepped synchronously."""
+
+    def __init__(self, n_slots=1000, max_ranges=64, fixed_bytes=1000, bad_rids=()):
+        self.n_slots = n_slots
+        self.max_ranges = max_ranges
+        self.fixed_bytes = fixed_bytes
+        self.bad_rids = set(bad_rids)
+        self.ranges = {}      # first slot -> request
+        self.admitted = []
         self.released = []
+        self.steps_taken = {}
 
     def footprint(self, req):
         s = req.spec
         d = 2 * s["r"] + 1
         obs_words = req.n_envs * s["n"] * s["C"] * ((d * d + 31) // 32)
         per_step = 4 * obs_words + 4 * req.n_envs * s["n"] + req.n_envs
-        return 1000 * req.n_envs + req.steps * per_step
+        return req.steps * per_step + 4 * obs_words
 
-    def create(self, req):
-        if req.rid in self.fail_rids:
-            raise RuntimeError("planted failure")
-        b = o.OracleBatch([req.spec] * req.n_envs, env_id_base=0)
+    def admit(self, req):
+        first, count = req.first_slot, req.n_envs
+        assert 0 <= first and first + count <= self.n_slots
+        for f, r in self.ranges.items():  # slots are never handed out twice
+            assert first + count <= f or f + r.n_envs <= first
+        b = o.OracleBatch([req.spec] * count, env_id_base=0)
         b.reset(req.seed)
-        outs = (np.zeros((req.steps, b.obs_total), np.uint32),
-                np.zeros((req.steps, b.agents_total), np.float32),
-                np.zeros((req.steps, b.n_envs), np.uint8))
-        self.created.append(req.rid)
-        return b, outs
+        req.outputs = dict(obs=np.zeros((req.steps, b.obs_total), np.uint32),
+                           rew=np.zeros((req.steps, b.agents_total), np.float32),
+                           done=np.zeros((req.steps, b.n_envs), np.uint8))
+        req._oracle = b
+        self.ranges[first] = req
+        self.steps_taken[req.rid] = 0
+        self.admitted.append(req.rid)
 
-    def step(self, items, n_steps):
-        assert all(k <= n_steps for _, k in items)
-        for r, k in items:
-            ob, rw, dn = r.batch.step(k)
-            s0 = r.done_steps
-            r.outputs[0][s0:s0 + k] = ob
-            r.outputs[1][s0:s0 + k] = rw
-            r.outputs[2][s0:s0 + k] = dn
-        return 1.0
+    def mark(self):
+        return Ev()
+
+    def step(self, n):
+        for r in self.ranges.values():
+            k = min(n, r.steps - self.steps_taken[r.rid])
+            if k:
+                ob, rw, dn = r._oracle.step(k)
+                s0 = self.steps_taken[r.rid]
+                r.outputs["obs"][s0:s0 + k] = ob
+                r.outputs["rew"][s0:s0 + k] = rw
+                r.outputs["done"][s0:s0 + k] = dn
+                self.steps_taken[r.rid] += k
 
     def release(self, req):
+        del self.ranges[req.first_slot]
         self.released.append(req.rid)
-        req.batch = None
+
+    @staticmethod
+    def done(ev):
+        return ev.query()
+
+    @staticmethod
+    def wait(ev):
+        pass
+
+    @staticmethod
+    def elapsed_ms(a, b):
+        return 1.0
+
+    def check(self, req):
+        return "planted reset failure" if req.rid in self.bad_rids else ""
 
 
-def make_reqs(n, seed=3):
+def make_reqs(n, seed=3, envs=24, steps=70):
     tr = wl.serving_trace(n, rate_per_s=1000.0, seed=seed)
-    out = []
-    for t in tr:
-        out.append(serve.Request(t["rid"], t["spec"], min(t["n_envs"], 24), min(t["steps"], 70),
-                                 t["seed"]))
-    return out
+    return [serve.Request(t["rid"], t["spec"], min(t["n_envs"], envs), min(t["steps"], steps),
+                          t["seed"]) for t in tr]
 
 
 def alone(req):
@@ -65,8 +101,21 @@ def alone(req):
     return b.step(req.steps)
 
 
+def test_slot_allocator_first_fit_and_merge():
+    a = serve.SlotAllocator(100)
+    assert a.take(30) == 0 and a.take(30) == 30 and a.take(50) is None
+    a.give(0, 30)
+    assert a.take(10) == 0 and a.take(25) == 60 and a.take(20) == 10
+    a.give(30, 30)
+    a.give(10, 20)
+    a.give(0, 10)
+    assert a.free == [(0, 60), (85, 15)] and a.largest() == 60
+    a.give(60, 25)
+    assert a.free == [(0, 100)]
+
+
 def test_results_same_alone_and_in_mix():
-    ex = OracleExecutor()
+    ex = OracleArenaExecutor()
     srv = serve.Server(ex, budget_bytes=1 << 40, chunk=16)
     reqs = make_reqs(6)
     for r in reqs[:3]:
@@ -80,14 +129,43 @@ def test_results_same_alone_and_in_mix():
         assert r.state == "done"
         for got, want in zip(srv.fetch(r), alone(r)):
             assert np.array_equal(got, want)
-    assert srv.used == 0
+    assert srv.used == ex.fixed_bytes
+    assert sorted(ex.released) == sorted(r.rid for r in reqs)
+
+
+def test_fetch_hands_outputs_over():
+    """After fetch the server holds no reference to a request's outputs."""
+    ex = OracleArenaExecutor()
+    srv = serve.Server(ex, budget_bytes=1 << 40, chunk=32)
+    reqs = make_reqs(3, seed=7)
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    for r in reqs:
+        srv.fetch(r)
+    assert all(r.outputs is None for r in srv.finished)
+    with pytest.raises(RuntimeError):
+        srv.fetch(reqs[0])
+
+
+def test_admission_waits_for_slots_and_reuses_them():
+    ex = OracleArenaExecutor(n_slots=50)
+    srv = serve.Server(ex, budget_bytes=1 << 40, chunk=1000)
+    reqs = make_reqs(3, seed=4, envs=24)  # two fit at once, the third waits for slots
+    for r in reqs:
+        srv.submit(r)
+    srv.step_once()
+    assert [r.state for r in reqs] == ["done", "done", "queued"]
+    srv.step_once()
+    assert reqs[2].state == "done"
+    assert reqs[2].first_slot in (reqs[0].first_slot, reqs[1].first_slot)
 
 
 def test_admission_waits_for_budget_and_fetch():
-    ex = OracleExecutor()
+    ex = OracleArenaExecutor()
     reqs = make_reqs(3, seed=4)
     fp = [ex.footprint(r) for r in reqs]
-    srv = serve.Server(ex, budget_bytes=max(fp), chunk=1000)
+    srv = serve.Server(ex, budget_bytes=max(fp) + ex.fixed_bytes, chunk=1000)
     for r in reqs:
         srv.submit(r)
     assert srv.step_once()
@@ -101,18 +179,18 @@ def test_admission_waits_for_budget_and_fetch():
 
 
 def test_rejects_request_larger_than_budget():
-    ex = OracleExecutor()
+    ex = OracleArenaExecutor()
     r = make_reqs(1)[0]
-    srv = serve.Server(ex, budget_bytes=ex.footprint(r) - 1)
+    srv = serve.Server(ex, budget_bytes=ex.footprint(r) + ex.fixed_bytes - 1)
     srv.submit(r)
     assert r.state == "rejected"
     with pytest.raises(RuntimeError):
-        r.result(0)
+        srv.fetch(r, 0)
 
 
 def test_cancel_queued_and_failure_isolation():
     reqs = make_reqs(4, seed=6)
-    ex = OracleExecutor(fail_rids={reqs[1].rid})
+    ex = OracleArenaExecutor(bad_rids={reqs[1].rid})
     srv = serve.Server(ex, budget_bytes=1 << 40, chunk=8)
     for r in reqs:
         srv.submit(r)
@@ -124,12 +202,23 @@ def test_cancel_queued_and_failure_isolation():
         assert r.state == "done"
         for got, want in zip(srv.fetch(r), alone(r)):
             assert np.array_equal(got, want)
-    assert srv.used == 0
-    assert sorted(ex.released) == sorted([reqs[0].rid, reqs[2].rid])
+    assert srv.used == ex.fixed_bytes
+
+
+def test_range_table_limit_queues():
+    ex = OracleArenaExecutor(max_ranges=2)
+    srv = serve.Server(ex, budget_bytes=1 << 40, chunk=1000)
+    reqs = make_reqs(3, seed=8)
+    for r in reqs:
+        srv.submit(r)
+    srv.step_once()
+    assert [r.state for r in reqs] == ["done", "done", "queued"]
+    srv.drain()
+    assert reqs[2].state == "done"
 
 
 def test_background_thread_serves_concurrent_clients():
-    ex = OracleExecutor()
+    ex = OracleArenaExecutor()
     srv = serve.Server(ex, budget_bytes=1 << 40, chunk=16)
     srv.start()
     reqs = make_reqs(5, seed=9)
@@ -137,7 +226,7 @@ def test_background_thread_serves_concurrent_clients():
 
     def client(r):
         srv.submit(r)
-        res[r.rid] = srv.fetch(r)
+        res[r.rid] = srv.fetch(r, 60)
 
     th = [threading.Thread(target=client, args=(r,)) for r in reqs]
     for t in th:
@@ -148,5 +237,5 @@ def test_background_thread_serves_concurrent_clients():
     for r in reqs:
         for got, want in zip(res[r.rid], alone(r)):
             assert np.array_equal(got, want)
-    st = srv.stats()
+    st = srv.stats(1.0)
     assert st["requests_done"] == 5 and st["step_latency_ms_p99"] >= st["step_latency_ms_p50"]

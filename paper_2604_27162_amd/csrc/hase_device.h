@@ -1169,77 +1169,95 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 // agent's class may enter and (collisions on) free; then the
                 // move chance and, for a walker entering mud, the stuck chance
                 // decide, from words 2(i&1) and 2(i&1)+1 of the MOVE block of
-                // agent pair i>>1 at this step. Lane l of the env draws the
-                // blocks of pairs l, l + LANES, ...; every lane fetches the
-                // words it needs from their lanes.
-                constexpr int NPAIRS = (NMAX + 1) / 2;
-                constexpr int ROUNDS = (NPAIRS + LANES - 1) / LANES;
-                U4 blk[ROUNDS];
+                // agent pair i>>1 at this step. Everything but the
+                // occupancy test depends on the agent alone, so each lane
+                // decides it for its own agents (target, "moves if the
+                // target is free", "gets stuck if it moves"), the env's
+                // lanes exchange those words through the env's LDS respawn
+                // words, and every lane runs the sequential occupancy chain
+                // (agents in index order) on them.
+                uint32_t *xw = (uint32_t *)spawned;
 #pragma unroll
-                for (int rr = 0; rr < ROUNDS; ++rr)
-                    blk[rr] = philox(env, (ST_MOVE << 24) | (uint32_t)(rr * LANES + l), steps, 0u, k0, k1);
-                auto draw = [&](int i, bool second) __attribute__((always_inline)) {
-                    const int k = i >> 1, rr = k / LANES, src = k % LANES;
-                    const U4 b = blk[rr];
-                    const uint32_t w = pick((i & 1) != 0, pick(second, b.w, b.z), pick(second, b.y, b.x));
-                    if constexpr (LANES == 1)
-                        return w;
-                    else
-                        return (uint32_t)__shfl((int)w, q * LANES + src, 64);
-                };
-#pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    const uint32_t a = (uint32_t)(acts >> (3 * i)) & 7u;  // 0 for absent agents
-                    const int tg = pp[i] + (int)((MOVE_TABLE >> (12u * a)) & 0x3ffull) - 257;
+                for (int m = 0; m < TPL; ++m) {
+                    const int a = l + m * LANES;
+                    const uint32_t act = (uint32_t)(acts >> (3 * a)) & 7u;  // 0 for absent agents
+                    const int tg = mine[m] + (int)((MOVE_TABLE >> (12u * act)) & 0x3ffull) - 257;
                     uint32_t widx = (uint32_t)(tg >> 8) * (uint32_t)LDS_ROW + (((uint32_t)tg >> 5) & 7u);
                     widx = widx < (uint32_t)pw - 1u ? widx : (uint32_t)pw - 1u;  // parked agents
                     const uint32_t sh = (uint32_t)tg & 31u;
                     const uint32_t b0 = (slot[widx] >> sh) & 1u, b1 = (slot[pw + widx] >> sh) & 1u;
-                    const uint32_t cls = agent_class(clo, chi, i);
-                    uint32_t occ = 0u;
-#pragma unroll
-                    for (int jj = 0; jj < NMAX; ++jj)
-                        if (jj != i) occ |= ((uint32_t)(tg ^ pp[jj]) - 1u) >> 31;
-                    // every condition evaluated, combined with bitwise ops:
-                    // short-circuit && compiles to a branch per agent here
-                    const uint32_t blocked = ((stuck >> i) & 1u) | (class_blocked(cls, b0, b1) & 1u) |
-                                             (occ & cmask) | (a == 0u ? 1u : 0u);
-                    const uint32_t u = draw(i, false), v = draw(i, true);
+                    const uint32_t cls = agent_class(clo, chi, a);
+                    const U4 blk = philox(env, (ST_MOVE << 24) | ((uint32_t)a >> 1), steps, 0u, k0, k1);
+                    const bool odd = (a & 1) != 0;
+                    const uint32_t u = pick(odd, blk.z, blk.x), v = pick(odd, blk.w, blk.y);
                     const uint32_t type = b0 | (b1 << 1);  // ground, wall, water, mud
                     const uint32_t tile = (type + 1u) >> 1;  // ground 0, water 1, mud 2 (wall: blocked)
                     const uint32_t k = cls * 3u + tile;
                     const uint32_t pct = (pick(k < 4u, sp_a, pick(k < 8u, sp_b, sp_c)) >> (8u * (k & 3u))) & 0xffu;
+                    // every condition evaluated, combined with bitwise ops
+                    const uint32_t blocked = ((stuck >> (uint32_t)a) & 1u) | (class_blocked(cls, b0, b1) & 1u) |
+                                             (act == 0u ? 1u : 0u);
                     const uint32_t go = (chance(u, pct) ? 1u : 0u) & (blocked ^ 1u);
                     const uint32_t sticks = go & (cls == 0u ? 1u : 0u) & (type == 3u ? 1u : 0u) &
                                             (chance(v, (tch >> 16) & 0xffu) ? 1u : 0u);
-                    stuck |= sticks << i;
-                    pp[i] = go ? tg : pp[i];
+                    if (a < NMAX) xw[a] = (uint32_t)tg | (go << 16) | (sticks << 17);
                 }
-                // rescue: freed by a teammate that is not stuck within
-                // Chebyshev distance 1 after the moves ((dy + 1) << 8 | (dx + 1)
-                // has both bytes below 3 exactly then)
+                wave_lds_fence();
+                int tgt[NMAX];
+                uint32_t gof[NMAX], stk[NMAX], mpre[NMAX];
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    const uint32_t w = xw[i];
+                    tgt[i] = (int)(w & 0xffffu);
+                    gof[i] = (w >> 16) & 1u;
+                    stk[i] = (w >> 17) & 1u;
+                }
+                // the reads precede the radio exchange's and a respawn's
+                // writes to these words
+                wave_lds_fence();
+                // occupancy: the minimum of target ^ cell over the other
+                // agents is 0 exactly when the target is held; the part over
+                // agents that have not moved yet is taken ahead of the chain
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    uint32_t mn = 0xffffu;  // cells are below 2^16
+#pragma unroll
+                    for (int jj = i + 1; jj < NMAX; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
+                    mpre[i] = mn;
+                }
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    uint32_t mn = mpre[i];
+#pragma unroll
+                    for (int jj = 0; jj < i; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
+                    const uint32_t moved = gof[i] & ~(((mn - 1u) >> 31) & cmask);
+                    stuck |= (moved & stk[i]) << i;
+                    pp[i] = moved ? tgt[i] : pp[i];
+                }
+                // rescue: a stuck agent is freed by a teammate that is not
+                // stuck within Chebyshev distance 1 after the moves ((dy + 1)
+                // << 8 | (dx + 1) has both bytes below 3 exactly then); each
+                // lane tests its own agents, the env's lanes OR the results
                 const uint32_t before = stuck;
                 if (before != 0u) {
+                    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
                     const uint32_t smask = (1u << S) - 1u;  // seekers; hmask: hiders
-                    uint32_t nb[NMAX];  // agents within Chebyshev distance 1 of each
+                    uint32_t freed = 0u;
 #pragma unroll
-                    for (int i = 0; i < NMAX; ++i) nb[i] = 0u;
+                    for (int m = 0; m < TPL; ++m) {
+                        const int a = l + m * LANES;
+                        uint32_t near = 0u;
 #pragma unroll
-                    for (int i = 0; i < NMAX; ++i) {
-#pragma unroll
-                        for (int jj = i + 1; jj < NMAX; ++jj) {
-                            const uint32_t du = (uint32_t)(pp[i] - pp[jj]) + 257u;
+                        for (int jj = 0; jj < NMAX; ++jj) {
+                            const uint32_t du = (uint32_t)(mine[m] - pp[jj]) + 257u;
                             const uint32_t lo = du & 0xffu, hi = du >> 8;
-                            const uint32_t near = (lo > hi ? lo : hi) < 3u ? 1u : 0u;
-                            nb[i] |= near << jj;
-                            nb[jj] |= near << i;
+                            near |= ((lo > hi ? lo : hi) < 3u ? 1u : 0u) << jj;
                         }
+                        const uint32_t abit = a < 32 ? 1u << a : 0u;
+                        const uint32_t mates = (a < S ? smask : hmask) & ~abit;
+                        freed |= ((before & abit) != 0u && (near & mates & ~before) != 0u) ? abit : 0u;
                     }
-#pragma unroll
-                    for (int i = 0; i < NMAX; ++i) {
-                        const uint32_t mates = (i < S ? smask : hmask) & ~(1u << i);
-                        stuck &= (nb[i] & mates & ~before) != 0u ? ~(1u << i) : 0xffffffffu;
-                    }
+                    stuck &= ~group_or_dpp<LANES>(freed);
                 }
             } else if constexpr (NBR) {
                 // Integer decisions only: lane-mask logic would cost a round

@@ -1628,12 +1628,22 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     };
     // The feature loops use the exact per-agent channels, which are right
     // whether or not agents may share a cell; the distinct-cell shortcut is
-    // kept for the plain loop.
+    // kept for the plain loop and the two single-feature kinds below.
     if constexpr (KIND == KIND_PLAIN) {
         if (collide)
             run(std::false_type{}, std::integral_constant<int, 0>{});
         else
             run(std::true_type{}, std::integral_constant<int, 0>{});
+    } else if constexpr (KIND == KIND_TERRAIN || KIND == KIND_RADIO) {
+        // terrain alone and radio alone also take the shortcut when
+        // collisions keep agents on distinct cells (stuck agents stay put,
+        // rescue moves nobody, radio moves nobody): the exact test of every
+        // agent against every window cost terrain4k a quarter of its
+        // vector instructions
+        if (collide)
+            run(std::false_type{}, std::integral_constant<int, KIND>{});
+        else
+            run(std::true_type{}, std::integral_constant<int, KIND>{});
     } else {
         run(std::true_type{}, std::integral_constant<int, KIND>{});
     }
@@ -1703,8 +1713,11 @@ __device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobD
 // Mixed variants in one launch (uneven batches, feature kinds): each wave
 // runs the code of its own tile's (bucket, radius), chosen by a wave-uniform
 // switch, so every bucket of the batch shares the chip at once. One kernel
-// per env kind.
-template <int LANES, int KIND>
+// per env kind for the buckets of up to 10 agents and one for the bucket of
+// up to 20 (BIG): the registers a kernel gets are those of its heaviest
+// code, and with the 20-agent code inside, the 16-lane plain kernel needed
+// 292 VGPRs (one wave per SIMD) where the others need 238 (two).
+template <int LANES, int KIND, bool BIG>
 __global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__ tiles,
                                                         uint32_t n_tiles,
                                                         const JobDesc *__restrict__ jobs,
@@ -1720,11 +1733,15 @@ __global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__
     if (tile.count == 0u || (job0.group != ALL_GROUPS && (tile.variant >> 8) != job0.group)) return;
     const JobDesc J = jobs ? jobs[tile.job] : job0;
     const int bucket = (int)((tile.variant >> 2) & 3u), r = (int)(tile.variant & 3u) + 1;
-    switch (bucket) {
-    case 0: mixed_bucket<LANES, 0, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
-    case 1: mixed_bucket<LANES, 1, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
-    case 2: mixed_bucket<LANES, 2, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
-    default: mixed_bucket<LANES, 3, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+    if constexpr (BIG) {
+        if (bucket == 3) mixed_bucket<LANES, 3, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds);
+    } else {
+        switch (bucket) {
+        case 0: mixed_bucket<LANES, 0, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        case 1: mixed_bucket<LANES, 1, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        case 2: mixed_bucket<LANES, 2, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        default: break;
+        }
     }
 }
 
@@ -1776,12 +1793,17 @@ inline hipError_t launch_lanes(int nmax, int r, const Tile *tiles, uint32_t n_ti
 template <int LANES, int KIND>
 inline hipError_t launch_mixed_l(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
                                  const JobDesc &job0, uint32_t K, uint32_t step_base,
-                                 uint32_t slot_words, uint32_t map_words, hipStream_t stream)
+                                 uint32_t slot_words, uint32_t map_words, bool big,
+                                 hipStream_t stream)
 {
     const size_t lds =
         (size_t)(64 / LANES) * (slot_words + MAX_AGENTS + map_words) * sizeof(uint32_t);
-    hipLaunchKernelGGL((step_kernel_mixed<LANES, KIND>), dim3(n_tiles), dim3(64), lds, stream,
-                       tiles, n_tiles, jobs, job0, K, step_base, slot_words, map_words);
+    if (big)
+        hipLaunchKernelGGL((step_kernel_mixed<LANES, KIND, true>), dim3(n_tiles), dim3(64), lds,
+                           stream, tiles, n_tiles, jobs, job0, K, step_base, slot_words, map_words);
+    else
+        hipLaunchKernelGGL((step_kernel_mixed<LANES, KIND, false>), dim3(n_tiles), dim3(64), lds,
+                           stream, tiles, n_tiles, jobs, job0, K, step_base, slot_words, map_words);
     return hipGetLastError();
 }
 

@@ -105,12 +105,17 @@ struct JobDesc {
 // A wave's work: envs perm[env0 .. env0 + count) of job `job` (count <= 64 /
 // lanes; 0: an empty tile, skipped); variant = agent-count bucket * 4 + view
 // radius - 1 (read by the mixed-variant kernel), plus, for the tiles of an
-// arena, the launch group (env kind | lanes << 8) in bits 8 and up.
+// arena, the launch group (group_code) in bits 8 and up.
 struct Tile {
     uint32_t job, env0, count, variant;
 };
 constexpr uint32_t ALL_GROUPS = 0xffffffffu;
-constexpr uint32_t group_code(int kind, int lanes) { return (uint32_t)kind | ((uint32_t)lanes << 8); }
+// launch group of a tile: env kind, lanes per env, and whether its bucket is
+// the one of up to 20 agents (a kernel of its own)
+constexpr uint32_t group_code(int kind, int lanes, bool big)
+{
+    return (uint32_t)kind | ((uint32_t)lanes << 8) | (big ? 1u << 16 : 0u);
+}
 
 struct InitArgs {
     EnvTables tab;
@@ -175,7 +180,7 @@ hipError_t launch_step(int lanes, int nmax, int r, const Tile *tiles, uint32_t n
 // envs, else 0).
 hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles,
                         const JobDesc *jobs, const JobDesc &job0, uint32_t K, uint32_t step_base,
-                        uint32_t slot_words, uint32_t map_words, hipStream_t stream);
+                        uint32_t slot_words, uint32_t map_words, bool big, hipStream_t stream);
 
 hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 
@@ -196,28 +201,28 @@ hipError_t static_workspace(void **ptr);
                                     uint32_t step_base, uint32_t slot_words, hipStream_t stream); \
     hipError_t launch_mixed_lanes##L(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,   \
                                      const JobDesc &job0, uint32_t K, uint32_t step_base,         \
-                                     uint32_t slot_words, uint32_t map_words,                     \
+                                     uint32_t slot_words, uint32_t map_words, bool big,                     \
                                      hipStream_t stream);                                         \
     hipError_t launch_feat_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,               \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
-                                    uint32_t step_base, uint32_t slot_words, uint32_t map_words,  \
+                                    uint32_t step_base, uint32_t slot_words, uint32_t map_words, bool big,  \
                                     hipStream_t stream);                                          \
     hipError_t launch_terr_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,               \
                                     const JobDesc *jobs, const JobDesc &job0, uint32_t K,         \
-                                    uint32_t step_base, uint32_t slot_words, uint32_t map_words,  \
+                                    uint32_t step_base, uint32_t slot_words, uint32_t map_words, bool big,  \
                                     hipStream_t stream);                                          \
     hipError_t launch_terrlos_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,            \
                                        const JobDesc *jobs, const JobDesc &job0, uint32_t K,      \
                                        uint32_t step_base, uint32_t slot_words,                   \
-                                       uint32_t map_words, hipStream_t stream);                   \
+                                       uint32_t map_words, bool big, hipStream_t stream);                   \
     hipError_t launch_radio_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,              \
                                      const JobDesc *jobs, const JobDesc &job0, uint32_t K,        \
-                                     uint32_t step_base, uint32_t slot_words, uint32_t map_words, \
+                                     uint32_t step_base, uint32_t slot_words, uint32_t map_words, bool big, \
                                      hipStream_t stream);                                         \
     hipError_t launch_radioter_lanes##L(int kind, const Tile *tiles, uint32_t n_tiles,           \
                                         const JobDesc *jobs, const JobDesc &job0, uint32_t K,     \
                                         uint32_t step_base, uint32_t slot_words,                  \
-                                        uint32_t map_words, hipStream_t stream);
+                                        uint32_t map_words, bool big, hipStream_t stream);
 HASE_DECLARE_LANES(1)
 HASE_DECLARE_LANES(2)
 HASE_DECLARE_LANES(4)

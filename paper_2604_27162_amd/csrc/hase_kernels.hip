@@ -213,26 +213,26 @@ hipError_t launch_step(int lanes, int nmax, int r, const Tile *tiles, uint32_t n
 
 hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles,
                         const JobDesc *jobs, const JobDesc &job0, uint32_t K, uint32_t step_base,
-                        uint32_t slot_words, uint32_t map_words, hipStream_t stream)
+                        uint32_t slot_words, uint32_t map_words, bool big, hipStream_t stream)
 {
     if (n_tiles == 0) return hipSuccess;
 #define HASE_MIXED_CASE(L)                                                                          \
     case L:                                                                                         \
         if (kind == KIND_PLAIN)                                                                     \
             return launch_mixed_lanes##L(tiles, n_tiles, jobs, job0, K, step_base, slot_words,      \
-                                         map_words, stream);                                        \
+                                         map_words, big, stream);                                        \
         if (kind & KIND_RADIO) {                                                                    \
             if (kind & KIND_TERRAIN)                                                                \
                 return launch_radioter_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base,     \
-                                                slot_words, map_words, stream);                     \
+                                                slot_words, map_words, big, stream);                     \
             return launch_radio_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base,            \
-                                         slot_words, map_words, stream);                            \
+                                         slot_words, map_words, big, stream);                            \
         }                                                                                           \
         if (kind & KIND_TERRAIN)                                                                    \
             return launch_terr_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base, slot_words, \
-                                        map_words, stream);                                         \
+                                        map_words, big, stream);                                         \
         return launch_feat_lanes##L(kind, tiles, n_tiles, jobs, job0, K, step_base, slot_words,     \
-                                    map_words, stream);
+                                    map_words, big, stream);
     switch (lanes) {
     HASE_MIXED_CASE(1)
     HASE_MIXED_CASE(2)

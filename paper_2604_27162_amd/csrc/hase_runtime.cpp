@@ -221,13 +221,15 @@ int make_plan(const hase_batch_desc *d, Plan &p)
 struct Variant {
     int lanes = 0, nmax = 0, r = 0, kind = KIND_PLAIN;
     // mixed: the per-tile variant switch (the feature kinds have only that
-    // kernel); xpl: an env explores (LDS discovery maps of map_words)
-    bool mixed = false, xpl = false;
+    // kernel); xpl: an env explores (LDS discovery maps of map_words); big:
+    // the bucket of up to 20 agents, whose mixed kernel is its own
+    bool mixed = false, xpl = false, big = false;
     uint32_t tile0 = 0, n_tiles = 0, slot_words = 0, map_words = 0;
 };
 
-// lanes x kinds launches at most, each on its own stream when forked
-constexpr int MAX_LAUNCHES = 5 * N_KINDS;
+// lanes x kinds x (big or not) launches at most, each on its own stream
+// when forked
+constexpr int MAX_LAUNCHES = 5 * N_KINDS * 2;
 
 struct GraphEntry {
     uint32_t n_steps;
@@ -254,6 +256,7 @@ struct hase_batch {
     // cells and cap_n agents; ranges of slots admitted by hase_reset_range
     struct Range {
         uint32_t count, job, kind, lanes, n_tiles, slot_words, map_words;
+        bool big;
     };
     bool arena = false;
     uint32_t cap_h = 0, cap_w = 0, cap_n = 0;
@@ -306,14 +309,17 @@ int build_tiles(hase_batch *b)
     std::vector<Variant> vars;
     const uint32_t lane_order[] = {1, 2, 4, 8, 16};
     for (uint32_t L : lane_order) {
-        for (int kind = 0; kind < N_KINDS; ++kind) {
+        for (int kb = 0; kb < 2 * N_KINDS; ++kb) {
+            const int kind = kb >> 1;
+            const bool big = (kb & 1) != 0;
             Variant grp;
             grp.lanes = (int)L;
             grp.kind = kind;
+            grp.big = big;
             grp.tile0 = (uint32_t)tiles.size();
             int n_var = 0;
             for (int bk = 0; bk < N_BUCKETS; ++bk) {
-                if (b->lanes[bk] != L) continue;
+                if (b->lanes[bk] != L || (bk == N_BUCKETS - 1) != big) continue;
                 for (int r = 1; r <= PAD; ++r) {
                     std::vector<uint32_t> ids;
                     for (uint32_t e = 0; e < N; ++e) {
@@ -428,7 +434,7 @@ int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, h
         }
         if (v.mixed)
             HIP_TRY(launch_mixed(v.lanes, v.kind, tiles + v.tile0, v.n_tiles, nullptr, job, K,
-                                 step_base, v.slot_words, v.map_words, s));
+                                 step_base, v.slot_words, v.map_words, v.big, s));
         else
             HIP_TRY(launch_step(v.lanes, v.nmax, v.r, tiles + v.tile0, v.n_tiles, nullptr, job, K,
                                 step_base, v.slot_words, s));
@@ -1077,21 +1083,40 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
     struct Group {
         uint32_t lanes = 0, tile0 = 0, n_tiles = 0, slot = 0, map = 0, code0 = 0;
         int kind = KIND_PLAIN;
-        bool mixed = false;
+        bool mixed = false, big = false;
     };
     std::vector<Tile> tiles;
     std::vector<Group> groups;
     const uint32_t lane_order[] = {1, 2, 4, 8, 16};
     for (uint32_t L : lane_order) {
-        for (int kind = 0; kind < N_KINDS; ++kind) {
+        for (int kb = 0; kb < 2 * N_KINDS; ++kb) {
+            const int kind = kb >> 1;
+            const bool big = (kb & 1) != 0;
             Group g;
-            g.lanes = L;
-            g.kind = kind;
-            g.mixed = kind != KIND_PLAIN;  // the feature kinds have only the mixed kernel
-            g.tile0 = (uint32_t)tiles.size();
+            auto open_group = [&]() {
+                g = Group{};
+                g.lanes = L;
+                g.kind = kind;
+                g.big = big;
+                g.mixed = kind != KIND_PLAIN;  // the feature kinds have only the mixed kernel
+                g.tile0 = (uint32_t)tiles.size();
+            };
+            auto close_group = [&]() {
+                g.n_tiles = (uint32_t)tiles.size() - g.tile0;
+                if (g.n_tiles) groups.push_back(g);
+            };
+            open_group();
             for (uint32_t i = 0; i < n; ++i) {
                 for (const Variant &v : bs[i]->variants) {
-                    if ((uint32_t)v.lanes != L || v.kind != kind) continue;
+                    if ((uint32_t)v.lanes != L || v.kind != kind || v.big != big) continue;
+                    // a request whose boards would push the group past 64 KiB of
+                    // LDS per wave starts a launch group of its own
+                    const uint32_t slot = std::max(g.slot, v.slot_words), map = std::max(g.map, v.map_words);
+                    if ((size_t)(64u / L) * (slot + MAX_AGENTS + map) * 4 > 65536 &&
+                        tiles.size() > g.tile0) {
+                        close_group();
+                        open_group();
+                    }
                     for (uint32_t t = v.tile0; t < v.tile0 + v.n_tiles; ++t) {
                         Tile tl = bs[i]->host_tiles[t];
                         tl.job = i;
@@ -1105,13 +1130,12 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
                     g.map = std::max(g.map, v.map_words);
                 }
             }
-            if ((size_t)(64u / L) * (g.slot + MAX_AGENTS + g.map) * 4 > 65536)
-                return fail(HASE_EINVAL,
-                            "requests with %u lanes/env need more than 64 KiB of LDS per wave", L);
-            g.n_tiles = (uint32_t)tiles.size() - g.tile0;
-            if (g.n_tiles) groups.push_back(g);
+            close_group();
         }
     }
+    if (groups.size() > (size_t)MAX_LAUNCHES)
+        return fail(HASE_EINVAL, "these requests need %zu launch groups, at most %d", groups.size(),
+                    MAX_LAUNCHES);
     char *ws = static_cast<char *>(d_workspace);
     const size_t jobs_bytes = align256(sizeof(JobDesc) * n);
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1138,7 +1162,7 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
         }
         if (g.mixed)
             HIP_TRY(launch_mixed((int)g.lanes, g.kind, dtiles + g.tile0, g.n_tiles, djobs, jobs[0],
-                                 n_steps, 0, g.slot, g.map, s));
+                                 n_steps, 0, g.slot, g.map, g.big, s));
         else
             HIP_TRY(launch_step((int)g.lanes, BUCKET_NMAX[g.code0 >> 2], (int)(g.code0 & 3u) + 1,
                                 dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps, 0, g.slot, s));
@@ -1364,7 +1388,8 @@ int hase_reset_range(hase_batch *b, uint32_t first_slot, uint32_t count, const h
     a.s2 = s.wall_pct | ((uint32_t)board_words_per_row(s.width) << 8);
     a.env_id_base = env_id_base;
     a.lanes = lanes;
-    a.variant = (uint32_t)(bk * 4 + s.view_radius - 1) | (group_code(kind, (int)lanes) << 8);
+    const bool big = bk == N_BUCKETS - 1;
+    a.variant = (uint32_t)(bk * 4 + s.view_radius - 1) | (group_code(kind, (int)lanes, big) << 8);
     if (s.flags & HASE_TERRAIN) {
         a.terr_words[0] = s.water_pct | ((uint32_t)s.mud_pct << 8) | ((uint32_t)s.stuck_pct << 16);
         for (int k = 0; k < 9; ++k) a.terr_words[1 + k / 4] |= (uint32_t)s.speed_pct[k] << (8 * (k % 4));
@@ -1386,10 +1411,11 @@ int hase_reset_range(hase_batch *b, uint32_t first_slot, uint32_t count, const h
         j0.obs = out->obs0;
         j0.obs_stride = 0;
         HIP_TRY(launch_mixed((int)lanes, kind, b->at<Tile>(r.tiles) + first_slot, n_tiles, nullptr, j0,
-                             0, 0, slot_words, mwl, b->stream));
+                             0, 0, slot_words, mwl, big, b->stream));
     }
     b->free_jobs.pop_back();
-    b->ranges[first_slot] = hase_batch::Range{count, job, (uint32_t)kind, lanes, n_tiles, slot_words, mwl};
+    b->ranges[first_slot] =
+        hase_batch::Range{count, job, (uint32_t)kind, lanes, n_tiles, slot_words, mwl, big};
     return HASE_OK;
 }
 
@@ -1434,15 +1460,16 @@ int hase_step_resident(hase_batch *b, uint32_t n_steps)
     // ones); groups run concurrently on forked streams
     struct G {
         uint32_t kind, lanes, extent, slot, map;
+        bool big;
     };
     std::vector<G> groups;
     for (const auto &kv : b->ranges) {
         const hase_batch::Range &rg = kv.second;
         G *g = nullptr;
         for (G &x : groups)
-            if (x.kind == rg.kind && x.lanes == rg.lanes) g = &x;
+            if (x.kind == rg.kind && x.lanes == rg.lanes && x.big == rg.big) g = &x;
         if (!g) {
-            groups.push_back(G{rg.kind, rg.lanes, 0u, rg.slot_words, rg.map_words});
+            groups.push_back(G{rg.kind, rg.lanes, 0u, rg.slot_words, rg.map_words, rg.big});
             g = &groups.back();
         }
         g->extent = std::max(g->extent, kv.first + rg.n_tiles);
@@ -1459,14 +1486,14 @@ int hase_step_resident(hase_batch *b, uint32_t n_steps)
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const G &g = groups[gi];
         JobDesc filter{};
-        filter.group = group_code((int)g.kind, (int)g.lanes);
+        filter.group = group_code((int)g.kind, (int)g.lanes, g.big);
         hipStream_t st = b->stream;
         if (fork && gi > 0) {
             HIP_TRY(hipStreamWaitEvent(b->side[gi], b->fork_ev, 0));
             st = b->side[gi];
         }
         HIP_TRY(launch_mixed((int)g.lanes, (int)g.kind, tiles, g.extent, jobs, filter, n_steps, 0,
-                             g.slot, g.map, st));
+                             g.slot, g.map, g.big, st));
         if (fork && gi > 0) {
             HIP_TRY(hipEventRecord(b->join_ev[gi], st));
             HIP_TRY(hipStreamWaitEvent(b->stream, b->join_ev[gi], 0));

@@ -6,15 +6,15 @@ namespace hase {
 
 hipError_t launch_terrlos_lanes1(int kind, const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
                                  const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
-                                 uint32_t map_words, hipStream_t stream)
+                                 uint32_t map_words, bool big, hipStream_t stream)
 {
     switch (kind) {
     case KIND_TERRAIN | KIND_LOS:
         return launch_mixed_l<1, KIND_TERRAIN | KIND_LOS>(tiles, n_tiles, jobs, job0, K, step_base,
-                                                          slot_words, map_words, stream);
+                                                          slot_words, map_words, big, stream);
     case KIND_TERRAIN | KIND_LOS | KIND_EXPLORE:
         return launch_mixed_l<1, KIND_TERRAIN | KIND_LOS | KIND_EXPLORE>(tiles, n_tiles, jobs, job0, K, step_base,
-                                                                         slot_words, map_words, stream);
+                                                                         slot_words, map_words, big, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,19 @@
+// The two-width kernel of the plain envs of uneven batches (4 lanes per env
+// for up to 4 agents, 16 for up to 10, one launch).
+#include "hase_device.h"
+
+namespace hase {
+
+hipError_t launch_combo(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
+                        const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
+                        hipStream_t stream)
+{
+    if (n_tiles == 0) return hipSuccess;
+    // the 4-lane tiles hold 16 envs per wave: the LDS of the wider slot array
+    const size_t lds = (size_t)16 * (slot_words + MAX_AGENTS) * sizeof(uint32_t);
+    hipLaunchKernelGGL((step_kernel_combo<KIND_PLAIN>), dim3(n_tiles), dim3(64), lds, stream, tiles,
+                       n_tiles, jobs, job0, K, step_base, slot_words, 0u);
+    return hipGetLastError();
+}
+
+}  // namespace hase

@@ -1745,6 +1745,42 @@ __global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__
     }
 }
 
+// Plain envs of an uneven batch in one launch at two widths: the buckets of
+// up to 2 and up to 4 agents at 4 lanes per env (16 envs per wave), those
+// buckets and the one of up to 10 agents at 16 lanes (bit 4 of a tile's
+// variant set). One grid keeps every SIMD busy to the end, where two launch
+// groups of different widths finish at different times, and small envs
+// need not spread over 16 lanes.
+template <int KIND>
+__global__ __launch_bounds__(64) void step_kernel_combo(const Tile *__restrict__ tiles,
+                                                        uint32_t n_tiles,
+                                                        const JobDesc *__restrict__ jobs,
+                                                        JobDesc job0, uint32_t K,
+                                                        uint32_t step_base, uint32_t slot_words,
+                                                        uint32_t map_words)
+{
+    extern __shared__ uint32_t lds[];
+    if (blockIdx.x >= n_tiles) return;
+    const Tile tile = tiles[blockIdx.x];
+    if (tile.count == 0u || (job0.group != ALL_GROUPS && (tile.variant >> 8) != job0.group)) return;
+    const JobDesc J = jobs ? jobs[tile.job] : job0;
+    const int bucket = (int)((tile.variant >> 2) & 3u), r = (int)(tile.variant & 3u) + 1;
+    if ((tile.variant >> 4) & 1u) {
+        switch (bucket) {
+        case 0: mixed_bucket<16, 0, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        case 1: mixed_bucket<16, 1, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        case 2: mixed_bucket<16, 2, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        default: break;
+        }
+    } else {
+        switch (bucket) {
+        case 0: mixed_bucket<4, 0, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        case 1: mixed_bucket<4, 1, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
+        default: break;
+        }
+    }
+}
+
 // ------------------------------------------------------------ launch helpers
 
 template <int LANES, int NMAX, int R>

@@ -182,6 +182,14 @@ hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles
                         const JobDesc *jobs, const JobDesc &job0, uint32_t K, uint32_t step_base,
                         uint32_t slot_words, uint32_t map_words, bool big, hipStream_t stream);
 
+// The plain envs of an uneven batch whose buckets take 4 lanes per env (up
+// to 4 agents) and 16 (up to 10 agents) in one launch: tiles of 16 lanes per
+// env have bit 4 of their variant set (hase_combo.hip).
+constexpr uint32_t COMBO_WIDE = 16u;
+hipError_t launch_combo(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
+                        const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
+                        hipStream_t stream);
+
 hipError_t launch_init(const InitArgs &a, hipStream_t stream);
 
 // Bytes of the library's static device workspace (per GPU) and the device

@@ -68,14 +68,20 @@ int bucket_of(int n)
 // Built-in lanes per env for each agent-count bucket (overridable by the tiler).
 const uint32_t DEFAULT_LANES[N_BUCKETS] = {4, 4, 16, 16};
 
-// Default tiling of a batch: the built-in lanes per bucket; but when the
-// buckets with the widest built-in lanes hold at least half of the batch's
-// agents, every bucket takes those lanes, so the whole batch is one launch
-// group (one kernel keeps all SIMDs busy to the end, instead of two groups
-// finishing at different times: uneven8k 7.1 -> 6.4 ms per 2000 steps, the
-// tiling the autotuner finds there).
+// Default tiling of a batch: the built-in lanes per bucket. A batch of plain
+// envs only keeps them (its 4- and 16-lane envs share one two-width launch);
+// otherwise, when the buckets with the widest built-in lanes hold at least
+// half of the batch's agents, every bucket takes those lanes, so the whole
+// batch is one launch group (one kernel keeps all SIMDs busy to the end,
+// instead of two groups finishing at different times).
 void default_lanes(const std::vector<hase_env_spec> &specs, uint32_t out[N_BUCKETS])
 {
+    bool all_plain = true;
+    for (const hase_env_spec &s : specs) all_plain = all_plain && env_kind(s.flags) == KIND_PLAIN;
+    if (all_plain) {
+        for (int bk = 0; bk < N_BUCKETS; ++bk) out[bk] = DEFAULT_LANES[bk];
+        return;
+    }
     uint64_t agents[N_BUCKETS] = {}, total = 0;
     for (const hase_env_spec &s : specs) {
         agents[bucket_of(s.n_agents)] += s.n_agents;
@@ -222,14 +228,15 @@ struct Variant {
     int lanes = 0, nmax = 0, r = 0, kind = KIND_PLAIN;
     // mixed: the per-tile variant switch (the feature kinds have only that
     // kernel); xpl: an env explores (LDS discovery maps of map_words); big:
-    // the bucket of up to 20 agents, whose mixed kernel is its own
-    bool mixed = false, xpl = false, big = false;
+    // the bucket of up to 20 agents, whose mixed kernel is its own; combo:
+    // the two-width launch of plain envs at 4 and 16 lanes
+    bool mixed = false, xpl = false, big = false, combo = false;
     uint32_t tile0 = 0, n_tiles = 0, slot_words = 0, map_words = 0;
 };
 
-// lanes x kinds x (big or not) launches at most, each on its own stream
-// when forked
-constexpr int MAX_LAUNCHES = 5 * N_KINDS * 2;
+// lanes x kinds x (big or not) launches at most, plus the two-width one,
+// each on its own stream when forked
+constexpr int MAX_LAUNCHES = 5 * N_KINDS * 2 + 1;
 
 struct GraphEntry {
     uint32_t n_steps;
@@ -307,6 +314,53 @@ int build_tiles(hase_batch *b)
     perm.reserve(N);
     std::vector<Tile> tiles;
     std::vector<Variant> vars;
+    // plain envs whose bucket takes 4 lanes (up to 4 agents) or 16 (up to 10)
+    // go to one two-width launch when both widths occur
+    auto in_combo = [&](int bk) {
+        return bk < N_BUCKETS - 1 && ((b->lanes[bk] == 4 && bk <= 1) || b->lanes[bk] == 16);
+    };
+    bool has4 = false, has16 = false;
+    for (const hase_env_spec &s : p.specs) {
+        const int bk = bucket_of(s.n_agents);
+        if (env_kind(s.flags) == KIND_PLAIN && in_combo(bk)) (b->lanes[bk] == 4 ? has4 : has16) = true;
+    }
+    const bool combo = has4 && has16;
+    if (combo) {
+        Variant grp;
+        grp.lanes = 4;  // LDS of 16 env slots per wave
+        grp.kind = KIND_PLAIN;
+        grp.mixed = grp.combo = true;
+        grp.tile0 = (uint32_t)tiles.size();
+        for (uint32_t L : {4u, 16u}) {
+            for (int bk = 0; bk < N_BUCKETS; ++bk) {
+                if (b->lanes[bk] != L || !in_combo(bk)) continue;
+                for (int r = 1; r <= PAD; ++r) {
+                    const uint32_t base = (uint32_t)perm.size();
+                    for (uint32_t e = 0; e < N; ++e) {
+                        const hase_env_spec &s = p.specs[e];
+                        if (bucket_of(s.n_agents) == bk && s.view_radius == r &&
+                            env_kind(s.flags) == KIND_PLAIN) {
+                            perm.push_back(e);
+                            grp.slot_words = std::max(grp.slot_words, (uint32_t)board_words(s.height, 1));
+                        }
+                    }
+                    const uint32_t cnt = (uint32_t)perm.size() - base, E = 64u / L;
+                    for (uint32_t i = 0; i < cnt; i += E) {
+                        Tile t;
+                        t.job = 0;
+                        t.env0 = base + i;
+                        t.count = std::min<uint32_t>(E, cnt - i);
+                        t.variant = (uint32_t)(bk * 4 + r - 1) | (L == 16 ? COMBO_WIDE : 0u);
+                        tiles.push_back(t);
+                    }
+                }
+            }
+        }
+        grp.n_tiles = (uint32_t)tiles.size() - grp.tile0;
+        if ((size_t)16 * (grp.slot_words + MAX_AGENTS) * 4 > 65536)
+            return fail(HASE_EINVAL, "tiling: the two-width launch needs more than 64 KiB of LDS per wave");
+        vars.push_back(grp);
+    }
     const uint32_t lane_order[] = {1, 2, 4, 8, 16};
     for (uint32_t L : lane_order) {
         for (int kb = 0; kb < 2 * N_KINDS; ++kb) {
@@ -320,6 +374,7 @@ int build_tiles(hase_batch *b)
             int n_var = 0;
             for (int bk = 0; bk < N_BUCKETS; ++bk) {
                 if (b->lanes[bk] != L || (bk == N_BUCKETS - 1) != big) continue;
+                if (combo && kind == KIND_PLAIN && in_combo(bk)) continue;
                 for (int r = 1; r <= PAD; ++r) {
                     std::vector<uint32_t> ids;
                     for (uint32_t e = 0; e < N; ++e) {
@@ -432,7 +487,9 @@ int enqueue(hase_batch *b, const JobDesc &job, uint32_t K, uint32_t step_base, h
             HIP_TRY(hipStreamWaitEvent(b->side[i], b->fork_ev, 0));
             s = b->side[i];
         }
-        if (v.mixed)
+        if (v.combo)
+            HIP_TRY(launch_combo(tiles + v.tile0, v.n_tiles, nullptr, job, K, step_base, v.slot_words, s));
+        else if (v.mixed)
             HIP_TRY(launch_mixed(v.lanes, v.kind, tiles + v.tile0, v.n_tiles, nullptr, job, K,
                                  step_base, v.slot_words, v.map_words, v.big, s));
         else
@@ -1083,22 +1140,25 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
     struct Group {
         uint32_t lanes = 0, tile0 = 0, n_tiles = 0, slot = 0, map = 0, code0 = 0;
         int kind = KIND_PLAIN;
-        bool mixed = false, big = false;
+        bool mixed = false, big = false, combo = false;
     };
     std::vector<Tile> tiles;
     std::vector<Group> groups;
     const uint32_t lane_order[] = {1, 2, 4, 8, 16};
     for (uint32_t L : lane_order) {
-        for (int kb = 0; kb < 2 * N_KINDS; ++kb) {
-            const int kind = kb >> 1;
-            const bool big = (kb & 1) != 0;
+        for (int kb = 0; kb < 4 * N_KINDS; ++kb) {
+            const int kind = (kb >> 1) % N_KINDS;
+            const bool big = (kb & 1) != 0, combo = kb >= 2 * N_KINDS;
+            if (combo && (L != 4 || kind != KIND_PLAIN || big)) continue;
             Group g;
             auto open_group = [&]() {
                 g = Group{};
                 g.lanes = L;
                 g.kind = kind;
                 g.big = big;
-                g.mixed = kind != KIND_PLAIN;  // the feature kinds have only the mixed kernel
+                g.combo = combo;
+                // the feature kinds have only the mixed kernel
+                g.mixed = kind != KIND_PLAIN || combo;
                 g.tile0 = (uint32_t)tiles.size();
             };
             auto close_group = [&]() {
@@ -1108,7 +1168,8 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
             open_group();
             for (uint32_t i = 0; i < n; ++i) {
                 for (const Variant &v : bs[i]->variants) {
-                    if ((uint32_t)v.lanes != L || v.kind != kind || v.big != big) continue;
+                    if ((uint32_t)v.lanes != L || v.kind != kind || v.big != big || v.combo != combo)
+                        continue;
                     // a request whose boards would push the group past 64 KiB of
                     // LDS per wave starts a launch group of its own
                     const uint32_t slot = std::max(g.slot, v.slot_words), map = std::max(g.map, v.map_words);
@@ -1160,7 +1221,9 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
             HIP_TRY(hipStreamWaitEvent(fb->side[gi], fb->fork_ev, 0));
             s = fb->side[gi];
         }
-        if (g.mixed)
+        if (g.combo)
+            HIP_TRY(launch_combo(dtiles + g.tile0, g.n_tiles, djobs, jobs[0], n_steps, 0, g.slot, s));
+        else if (g.mixed)
             HIP_TRY(launch_mixed((int)g.lanes, g.kind, dtiles + g.tile0, g.n_tiles, djobs, jobs[0],
                                  n_steps, 0, g.slot, g.map, g.big, s));
         else

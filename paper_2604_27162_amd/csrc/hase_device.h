@@ -839,6 +839,10 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // with at most 4 agents and 2 or 4 lanes the window is gathered by DPP and
     // spans exactly LANES steps
     constexpr bool DPP_WINDOW = WINDOWED && NMAX <= 4 && (LANES == 2 || LANES == 4);
+    // external actions of windowed loops (without radio, whose targets come
+    // with the action bytes) are read a window ahead and merged into the
+    // window's generator blocks, so no step waits for its action bytes
+    constexpr bool WIN_ACT = WINDOWED && (KIND & KIND_RADIO) == 0;
     // with at most 4 agents the wall tests of the moves come from bits kept
     // from the previous step's windows instead of board reads, and detection
     // (rewards, found bits) is a pairwise Chebyshev test in every lane of the
@@ -1143,8 +1147,9 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 }
             }
             // ---- 1 external actions override the drawn ones (-1 keeps the
-            // draw); with radio a value v >= 0 moves v mod 5
-            if (has_act) {
+            // draw); with radio a value v >= 0 moves v mod 5. The windowed
+            // loops without radio merge them into the window's blocks.
+            if (has_act && !WIN_ACT) {
                 uint64_t ov = 0, om = 0;
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
@@ -1542,35 +1547,110 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             return range_map(x.x, 5u) | (range_map(x.y, 5u) << 3) | (range_map(x.z, 5u) << 6) |
                    (range_map(x.w, 5u) << 9);
         };
+        // External action bytes of agents 4g .. 4g+3 at step `row` of this
+        // launch, as loaded (byte i for agent 4g + i), and the bytes that
+        // count as draws (past the env's agents or past the launch's steps).
+        // Every load reads inside the buffer (rows and agents are clamped)
+        // and nothing branches per lane, so the loads of the next window are
+        // in flight while the current one runs; they are only looked at
+        // when merged into that window.
+        struct ExtBytes {
+            uint32_t b[4], draw;
+        };
+        const GAS int8_t *const act0 = act_p;
+        auto ext_bytes = [&](uint32_t row, uint32_t g) __attribute__((always_inline)) {
+            ExtBytes x;
+            x.draw = 0xffffffffu;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x.b[i] = 0u;
+            if (has_act) {
+                const uint32_t rr = row < nsteps ? row : nsteps - 1u;
+                const GAS int8_t *rp = act0 + (uint64_t)rr * J.agent_stride;
+                x.draw = row < nsteps ? 0u : 0xffffffffu;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int a = (int)(4u * g) + i;
+                    x.b[i] = (uint32_t)(uint8_t)rp[a < n ? a : n - 1];
+                    x.draw |= a < n ? 0u : 0xffu << (8 * i);
+                }
+            }
+            return x;
+        };
+        // a generator block's four 3-bit actions with the external bytes
+        // merged in (-1 keeps the draw, 0..4 replaces it, anything else stays)
+        auto merge_ext = [&](uint32_t drawn, const ExtBytes &x) __attribute__((always_inline)) {
+            if (!has_act) return drawn;
+            const uint32_t bytes = (x.b[0] | (x.b[1] << 8) | (x.b[2] << 16) | (x.b[3] << 24)) | x.draw;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = (int)(int8_t)(bytes >> (8 * i));
+                const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                drawn = v == -1 ? drawn : ((drawn & ~(7u << (3 * i))) | (a << (3 * i)));
+            }
+            return drawn;
+        };
 
         if constexpr (DPP_WINDOW) {
             // lane l draws the block of step steps + l; a window covers LANES steps
+            // (the external bytes of the next window are loaded while the
+            // current one runs)
             if constexpr (UNROLL && !OC) {
-                uint32_t k = 0;
-                for (; k + LANES <= nsteps; k += LANES) {
-                    const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+                // two copies of the unrolled loop, with and without external
+                // actions, so the loads of the next window stay in flight
+                // (with a run-time test around them, the join after it waited
+                // for every outstanding load)
+                auto window_loop = [&](auto with_act) __attribute__((always_inline)) {
+                    constexpr bool WA = decltype(with_act)::value;
+                    uint32_t k = 0;
+                    ExtBytes nb{};
+                    if constexpr (WA) nb = ext_bytes((uint32_t)l, 0u);
+                    for (; k + LANES <= nsteps; k += LANES) {
+                        const ExtBytes cb = nb;
+                        uint32_t drawn = block_actions(0u, steps + (uint32_t)l);
+                        if constexpr (WA) {
+                            nb = ext_bytes(k + LANES + (uint32_t)l, 0u);
+                            drawn = merge_ext(drawn, cb);
+                        }
+                        const uint64_t w = gather_window<LANES>(drawn);
 #pragma unroll
-                    for (int jw = 0; jw < LANES; ++jw) step((w >> (12 * jw)) & 0xfffull);
-                }
-                if (k < nsteps) {
-                    const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
-                    for (uint32_t jw = 0; k < nsteps; ++k, ++jw) step((w >> (12u * jw)) & 0xfffull);
-                }
+                        for (int jw = 0; jw < LANES; ++jw) step((w >> (12 * jw)) & 0xfffull);
+                    }
+                    if (k < nsteps) {
+                        uint32_t drawn = block_actions(0u, steps + (uint32_t)l);
+                        if constexpr (WA) drawn = merge_ext(drawn, nb);
+                        const uint64_t w = gather_window<LANES>(drawn);
+                        for (uint32_t jw = 0; k < nsteps; ++k, ++jw) step((w >> (12u * jw)) & 0xfffull);
+                    }
+                };
+                if (has_act)
+                    window_loop(std::true_type{});
+                else
+                    window_loop(std::false_type{});
             } else if constexpr (KIND == KIND_PLAIN) {
                 // one loop, the window drawn when its index wraps (measured
                 // faster than the nested form below for the plain loops)
                 uint64_t w = 0;
+                ExtBytes nb = ext_bytes((uint32_t)l, 0u);
                 for (uint32_t k = 0; k < nsteps; ++k) {
                     const uint32_t jw = k & (uint32_t)(LANES - 1);
-                    if (jw == 0u) w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+                    if (jw == 0u) {
+                        const ExtBytes cb = nb;
+                        nb = ext_bytes(k + LANES + (uint32_t)l, 0u);
+                        w = gather_window<LANES>(merge_ext(block_actions(0u, steps + (uint32_t)l), cb));
+                    }
                     step((w >> (12u * jw)) & 0xfffull);
                 }
             } else {
                 // the feature loops: one window per outer iteration (with the
                 // single-loop form the compiler threaded the wrap test into
                 // an irreducible loop)
+                ExtBytes nb = ext_bytes((uint32_t)l, 0u);
                 for (uint32_t left = nsteps; left != 0u;) {
-                    const uint64_t w = gather_window<LANES>(block_actions(0u, steps + (uint32_t)l));
+                    const ExtBytes cb = nb;
+                    nb = ext_bytes(nsteps - left + LANES + (uint32_t)l, 0u);
+                    const uint64_t w = gather_window<LANES>(
+                        WIN_ACT ? merge_ext(block_actions(0u, steps + (uint32_t)l), cb)
+                                : block_actions(0u, steps + (uint32_t)l));
                     const uint32_t nw = left < (uint32_t)LANES ? left : (uint32_t)LANES;
 #pragma unroll 1
                     for (uint32_t jw = 0; jw < nw; ++jw) step((w >> (12u * jw)) & 0xfffull);
@@ -1581,8 +1661,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             // lane l draws block (step + wstep, group wgroup) of the window
             uint32_t win = 0;
             int j = 0;
+            ExtBytes nb = ext_bytes((uint32_t)wstep, (uint32_t)wgroup);
             for (uint32_t k = 0; k < nsteps; ++k) {
-                if (j == 0) win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                if (j == 0) {
+                    const ExtBytes cb = nb;
+                    nb = ext_bytes(k + (uint32_t)kb + (uint32_t)wstep, (uint32_t)wgroup);
+                    win = merge_ext(block_actions((uint32_t)wgroup, steps + (uint32_t)wstep), cb);
+                }
                 uint64_t acts = 0;
 #pragma unroll
                 for (int g = 0; g < MAXCALLS; ++g) {
@@ -1596,8 +1681,12 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             }
         } else if constexpr (WINDOWED) {
             // the same, one window of kb steps per outer iteration
+            ExtBytes nb = ext_bytes((uint32_t)wstep, (uint32_t)wgroup);
             for (uint32_t left = nsteps; left != 0u;) {
-                const uint32_t win = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                const ExtBytes cb = nb;
+                nb = ext_bytes(nsteps - left + (uint32_t)kb + (uint32_t)wstep, (uint32_t)wgroup);
+                const uint32_t drawn = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                const uint32_t win = WIN_ACT ? merge_ext(drawn, cb) : drawn;
                 if constexpr (RWIN) rwin = block_targets((uint32_t)wgroup, steps + (uint32_t)wstep);
                 const uint32_t nw = left < (uint32_t)kb ? left : (uint32_t)kb;
 #pragma unroll 1

@@ -268,6 +268,26 @@ __device__ __forceinline__ uint32_t dpp_mov(uint32_t v)
 
 // Every lane of a 2- or 4-lane group gets the 12-bit blocks of all lanes of
 // its group, in lane order, via DPP broadcasts (quad_perm patterns).
+// Value of lane k of the caller's env (its LANES consecutive lanes, 2 or 4:
+// a quad permutation within the env's quad or pair of lanes).
+template <int LANES>
+__device__ __forceinline__ uint32_t env_lane_bcast(uint32_t v, int k)
+{
+    static_assert(LANES == 2 || LANES == 4, "quad broadcasts serve 2 or 4 lanes per env");
+    if constexpr (LANES == 4) {
+        switch (k) {
+        case 0: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x00, 0xF, 0xF, false);
+        case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x55, 0xF, 0xF, false);
+        case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xAA, 0xF, 0xF, false);
+        default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xFF, 0xF, 0xF, false);
+        }
+    } else {
+        // quad_perm [0, 0, 2, 2] or [1, 1, 3, 3]
+        if (k == 0) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xA0, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xF5, 0xF, 0xF, false);
+    }
+}
+
 template <int LANES>
 __device__ __forceinline__ uint64_t gather_window(uint32_t v)
 {
@@ -849,6 +869,10 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // env, independent of the observation masks
     constexpr bool NBR = NMAX <= 4 && (KIND & KIND_TERRAIN) == 0;
     constexpr bool PAIRS = NMAX <= 4;
+    // plain respawns of the DPP-window loops try the first LANES / NMAX draws
+    // of every agent side by side before running the spawn rule
+    constexpr bool FAST_SPAWN = DPP_WINDOW && (KIND & KIND_TERRAIN) == 0 && LANES >= NMAX;
+    constexpr int SA = FAST_SPAWN ? LANES / NMAX : 1;
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
 
     const int lane = (int)threadIdx.x;
@@ -964,6 +988,9 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     int mine[TPL];
     own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
+    // ceil(2^18 / Wd): (c * wdiv) >> 18 is c / Wd for every cell index c of
+    // the map (c < 2^12, Wd <= 64: the rounding error stays below 2^18)
+    const uint32_t wdiv = ((1u << 18) + (uint32_t)Wd - 1u) / (uint32_t)Wd;
     const uint32_t hmask = (uint32_t)(((1ull << n) - 1ull) & ~((1ull << S) - 1ull));
     const uint64_t amask = (1ull << (3 * n)) - 1ull;  // action bits of real agents
     const int ncalls = (n + 3) >> 2;
@@ -1487,11 +1514,66 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                         return (class_blocked(agent_class(clo, chi, i), b0, b1) & 1u) == 0u;
                     });
                 } else {
-                    spawn_agents(spawned, n, H, Wd, slot, env, k0, k1, ep);
-                }
-                wave_lds_fence();
+                    bool by_rule = true;
+                    if constexpr (FAST_SPAWN) {
+                        // The rule's first SA draws of every agent, made side
+                        // by side (draw j of agent i by lane j * NMAX + i of
+                        // the env) and broadcast to the env's lanes; when
+                        // each agent takes one of them, the placement is
+                        // settled in registers. Otherwise the rule runs in
+                        // full, from the first agent.
+                        const uint32_t cells = (uint32_t)(H * Wd);
+                        const U4 x = philox(env, (ST_SPAWN << 24) | (uint32_t)(l % NMAX), ep,
+                                            (uint32_t)(l / NMAX), k0, k1);
+                        const uint32_t mine_c = range_map(x.x, cells);
+                        int cpc[SA][NMAX];
+                        uint32_t cfree[SA][NMAX];
 #pragma unroll
-                for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
+                        for (int j = 0; j < SA; ++j) {
+#pragma unroll
+                            for (int i = 0; i < NMAX; ++i) {
+                                const uint32_t c = env_lane_bcast<LANES>(mine_c, j * NMAX + i);
+                                // c / Wd, exact for c < 2^12 and Wd <= 64
+                                const uint32_t y = (c * wdiv) >> 18, xx = c - y * (uint32_t)Wd;
+                                cpc[j][i] = (int)(((y + PAD) << 8) | (xx + PAD));
+                                cfree[j][i] = board_bit(slot, cpc[j][i]) ^ 1u;
+                            }
+                        }
+                        int np[NMAX];
+                        uint32_t all_ok = 1u;
+#pragma unroll
+                        for (int i = 0; i < NMAX; ++i) {
+                            uint32_t placed = 0u;
+                            int p = FAR_CELL;
+#pragma unroll
+                            for (int j = 0; j < SA; ++j) {
+                                uint32_t ok = cfree[j][i] & (placed ^ 1u);
+#pragma unroll
+                                for (int k = 0; k < i; ++k) ok &= cpc[j][i] != np[k] ? 1u : 0u;
+                                p = ok ? cpc[j][i] : p;
+                                placed |= ok;
+                            }
+                            np[i] = i < n ? p : FAR_CELL;
+                            all_ok &= (i < n) ? placed : 1u;
+                        }
+                        if (all_ok) {
+#pragma unroll
+                            for (int jj = 0; jj < NMAX; ++jj) pp[jj] = np[jj];
+                            by_rule = false;
+                        }
+                    }
+                    if (by_rule) {
+                        spawn_agents(spawned, n, H, Wd, slot, env, k0, k1, ep);
+                        wave_lds_fence();
+#pragma unroll
+                        for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
+                    }
+                }
+                if constexpr (TER) {
+                    wave_lds_fence();
+#pragma unroll
+                    for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
+                }
                 own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
                 all_masks<R, W, NMAX, TPL, EX, OC, TER>(slot, H, Wd, pp, l, LANES, mine, n, S,
                                                         want_out, LOS, false, wall, outm, team,

@@ -144,14 +144,6 @@ __device__ __forceinline__ void spawn_agents_if(int *out, int n, int H, int W, u
     }
 }
 
-// Plain spawn: any open cell of the board.
-__device__ __forceinline__ void spawn_agents(int *out, int n, int H, int W, const uint32_t *slot,
-                                             uint32_t env, uint32_t k0, uint32_t k1, uint32_t ep)
-{
-    spawn_agents_if(out, n, H, W, env, k0, k1, ep,
-                    [&](int, int pc) { return board_bit(slot, pc) == 0u; });
-}
-
 // ------------------------------------------------------------ terrain
 
 // Tile types are two board planes (plane 0 = wall or mud, plane 1 = water or
@@ -873,6 +865,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // of every agent side by side before running the spawn rule
     constexpr bool FAST_SPAWN = DPP_WINDOW && (KIND & KIND_TERRAIN) == 0 && LANES >= NMAX;
     constexpr int SA = FAST_SPAWN ? LANES / NMAX : 1;
+    // with 8 or 16 lanes per env each lane draws the first SL draws of its
+    // own agents (the env's respawn words hold NMAX * SL 16-bit cells); not
+    // for terrain, whose step loop then spilled more scalar registers and
+    // ran 5% slower (terrain4k)
+    constexpr bool LANE_SPAWN = !FAST_SPAWN && LANES >= 8 && (KIND & KIND_TERRAIN) == 0;
+    constexpr int SL = NMAX >= 20 ? 2 : 3;
+    static_assert(NMAX * SL <= 2 * MAX_AGENTS, "the draws fit the respawn words");
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
 
     const int lane = (int)threadIdx.x;
@@ -988,9 +987,6 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     int mine[TPL];
     own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
 
-    // ceil(2^18 / Wd): (c * wdiv) >> 18 is c / Wd for every cell index c of
-    // the map (c < 2^12, Wd <= 64: the rounding error stays below 2^18)
-    const uint32_t wdiv = ((1u << 18) + (uint32_t)Wd - 1u) / (uint32_t)Wd;
     const uint32_t hmask = (uint32_t)(((1ull << n) - 1ull) & ~((1ull << S) - 1ull));
     const uint64_t amask = (1ull << (3 * n)) - 1ull;  // action bits of real agents
     const int ncalls = (n + 3) >> 2;
@@ -1503,73 +1499,140 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 // the new episode starts with an empty discovery map
                 if constexpr (XP)
                     for (uint32_t i = (uint32_t)l; i < map_words; i += LANES) mslot[i] = 0u;
-                if constexpr (TER) {
-                    // and with nobody stuck; each agent on a tile of its class
-                    stuck = 0u;
-                    spawn_agents_if(spawned, n, H, Wd, env, k0, k1, ep, [&](int i, int pc) {
+                // the respawn: each agent on a cell it may stand on (terrain:
+                // a tile of its class), and nobody stuck
+                if constexpr (TER) stuck = 0u;
+                auto may_stand = [&](int i, int pc) __attribute__((always_inline)) {
+                    if constexpr (TER) {
                         const int yy = pc >> 8, xx = pc & 0xff;
                         const int wi = yy * LDS_ROW + (xx >> 5);
                         const uint32_t b0 = (slot[wi] >> (xx & 31)) & 1u;
                         const uint32_t b1 = (slot[pw + wi] >> (xx & 31)) & 1u;
                         return (class_blocked(agent_class(clo, chi, i), b0, b1) & 1u) == 0u;
-                    });
-                } else {
-                    bool by_rule = true;
-                    if constexpr (FAST_SPAWN) {
-                        // The rule's first SA draws of every agent, made side
-                        // by side (draw j of agent i by lane j * NMAX + i of
-                        // the env) and broadcast to the env's lanes; when
-                        // each agent takes one of them, the placement is
-                        // settled in registers. Otherwise the rule runs in
-                        // full, from the first agent.
-                        const uint32_t cells = (uint32_t)(H * Wd);
-                        const U4 x = philox(env, (ST_SPAWN << 24) | (uint32_t)(l % NMAX), ep,
-                                            (uint32_t)(l / NMAX), k0, k1);
-                        const uint32_t mine_c = range_map(x.x, cells);
-                        int cpc[SA][NMAX];
-                        uint32_t cfree[SA][NMAX];
+                    } else {
+                        return board_bit(slot, pc) == 0u;
+                    }
+                };
+                bool by_rule = true;
+                // ceil(2^18 / Wd): (c * wdiv) >> 18 is c / Wd for every cell
+                // index c of the map (c < 2^12, Wd <= 64: the rounding error
+                // stays below 2^18)
+                const uint32_t wdiv = ((1u << 18) + (uint32_t)Wd - 1u) / (uint32_t)Wd;
+                if constexpr (FAST_SPAWN) {
+                    // The rule's first SA draws of every agent, made side
+                    // by side (draw j of agent i by lane j * NMAX + i of
+                    // the env) and broadcast to the env's lanes; when
+                    // each agent takes one of them, the placement is
+                    // settled in registers. Otherwise the rule runs in
+                    // full, from the first agent.
+                    const uint32_t cells = (uint32_t)(H * Wd);
+                    const U4 x = philox(env, (ST_SPAWN << 24) | (uint32_t)(l % NMAX), ep,
+                                        (uint32_t)(l / NMAX), k0, k1);
+                    const uint32_t mine_c = range_map(x.x, cells);
+                    int cpc[SA][NMAX];
+                    uint32_t cfree[SA][NMAX];
 #pragma unroll
-                        for (int j = 0; j < SA; ++j) {
-#pragma unroll
-                            for (int i = 0; i < NMAX; ++i) {
-                                const uint32_t c = env_lane_bcast<LANES>(mine_c, j * NMAX + i);
-                                // c / Wd, exact for c < 2^12 and Wd <= 64
-                                const uint32_t y = (c * wdiv) >> 18, xx = c - y * (uint32_t)Wd;
-                                cpc[j][i] = (int)(((y + PAD) << 8) | (xx + PAD));
-                                cfree[j][i] = board_bit(slot, cpc[j][i]) ^ 1u;
-                            }
-                        }
-                        int np[NMAX];
-                        uint32_t all_ok = 1u;
+                    for (int j = 0; j < SA; ++j) {
 #pragma unroll
                         for (int i = 0; i < NMAX; ++i) {
-                            uint32_t placed = 0u;
-                            int p = FAR_CELL;
-#pragma unroll
-                            for (int j = 0; j < SA; ++j) {
-                                uint32_t ok = cfree[j][i] & (placed ^ 1u);
-#pragma unroll
-                                for (int k = 0; k < i; ++k) ok &= cpc[j][i] != np[k] ? 1u : 0u;
-                                p = ok ? cpc[j][i] : p;
-                                placed |= ok;
-                            }
-                            np[i] = i < n ? p : FAR_CELL;
-                            all_ok &= (i < n) ? placed : 1u;
-                        }
-                        if (all_ok) {
-#pragma unroll
-                            for (int jj = 0; jj < NMAX; ++jj) pp[jj] = np[jj];
-                            by_rule = false;
+                            const uint32_t c = env_lane_bcast<LANES>(mine_c, j * NMAX + i);
+                            // c / Wd, exact for c < 2^12 and Wd <= 64
+                            const uint32_t y = (c * wdiv) >> 18, xx = c - y * (uint32_t)Wd;
+                            cpc[j][i] = (int)(((y + PAD) << 8) | (xx + PAD));
+                            cfree[j][i] = board_bit(slot, cpc[j][i]) ^ 1u;
                         }
                     }
-                    if (by_rule) {
-                        spawn_agents(spawned, n, H, Wd, slot, env, k0, k1, ep);
+                    int np[NMAX];
+                    uint32_t all_ok = 1u;
+#pragma unroll
+                    for (int i = 0; i < NMAX; ++i) {
+                        uint32_t placed = 0u;
+                        int p = FAR_CELL;
+#pragma unroll
+                        for (int j = 0; j < SA; ++j) {
+                            uint32_t ok = cfree[j][i] & (placed ^ 1u);
+#pragma unroll
+                            for (int k = 0; k < i; ++k) ok &= cpc[j][i] != np[k] ? 1u : 0u;
+                            p = ok ? cpc[j][i] : p;
+                            placed |= ok;
+                        }
+                        np[i] = i < n ? p : FAR_CELL;
+                        all_ok &= (i < n) ? placed : 1u;
+                    }
+                    if (all_ok) {
+#pragma unroll
+                        for (int jj = 0; jj < NMAX; ++jj) pp[jj] = np[jj];
+                        by_rule = false;
+                    }
+                }
+                if constexpr (LANE_SPAWN) {
+                    // The rule's first SL draws of every agent, made by the
+                    // lane of the agent's task, each kept (as its packed
+                    // cell) only if the agent may stand there, in the
+                    // 16-bit halves of the env's respawn words (agent a's
+                    // draw j in half a * SL + j). An agent takes its first
+                    // kept draw; that is the rule's choice whenever no
+                    // earlier agent kept the same cell among its draws
+                    // (its own choice is one of them). If some agent
+                    // kept none, or such a cell is shared, the rule runs
+                    // in full, from the first agent.
+                    const uint32_t cells = (uint32_t)(H * Wd);
+                    uint16_t *cand = (uint16_t *)spawned;
+#pragma unroll
+                    for (int m = 0; m < TPL; ++m) {
+                        const int a = l + m * LANES;
+#pragma unroll 1
+                        for (int j = 0; j < SL; ++j) {
+                            const U4 x = philox(env, (ST_SPAWN << 24) | (uint32_t)a, ep, (uint32_t)j, k0, k1);
+                            const uint32_t c = range_map(x.x, cells);
+                            const uint32_t y = (c * wdiv) >> 18, xx = c - y * (uint32_t)Wd;
+                            const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
+                            const bool keep = a < n && may_stand(a, pc);
+                            if (a < NMAX) cand[a * SL + j] = (uint16_t)(keep ? pc : 0xffff);
+                        }
+                    }
+                    wave_lds_fence();
+                    uint32_t bad = 0u;
+                    int choice[TPL];
+#pragma unroll
+                    for (int m = 0; m < TPL; ++m) {
+                        const int a = l + m * LANES;
+                        uint32_t ch = 0xffffu;
+#pragma unroll
+                        for (int j = 0; j < SL; ++j) {
+                            const uint32_t v = a < NMAX ? cand[a * SL + j] : 0xffffu;
+                            ch = ch == 0xffffu ? v : ch;
+                        }
+                        // the draws of earlier agents, two per word (few
+                        // registers: this runs inside the step loop)
+                        uint32_t shared = 0u;
+                        const uint32_t *cw = (const uint32_t *)spawned;
+#pragma unroll 1
+                        for (int k = 0; 2 * k < a * SL; ++k) {
+                            const uint32_t w = cw[k];
+                            shared |= (w & 0xffffu) == ch ? 1u : 0u;
+                            shared |= (2 * k + 1 < a * SL && (w >> 16) == ch) ? 1u : 0u;
+                        }
+                        bad |= (a < n) ? (shared | (ch == 0xffffu ? 1u : 0u)) : 0u;
+                        choice[m] = (int)ch;
+                    }
+                    bad = group_or_dpp<LANES>(bad);
+                    // every read of the draws precedes the writes below
+                    wave_lds_fence();
+                    if (bad == 0u) {
+#pragma unroll
+                        for (int m = 0; m < TPL; ++m) {
+                            const int a = l + m * LANES;
+                            if (a < n) spawned[a] = choice[m];
+                        }
                         wave_lds_fence();
 #pragma unroll
                         for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
+                        by_rule = false;
                     }
                 }
-                if constexpr (TER) {
+                if (by_rule) {
+                    spawn_agents_if(spawned, n, H, Wd, env, k0, k1, ep, may_stand);
                     wave_lds_fence();
 #pragma unroll
                     for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;

@@ -280,6 +280,31 @@ __device__ __forceinline__ uint32_t env_lane_bcast(uint32_t v, int k)
     }
 }
 
+// Value of lane k of the caller's env when the env has 8 or 16 lanes (DPP
+// row broadcast of lane k of each 16-lane row; with 8 lanes per env the
+// upper env of a row takes lane 8 + k).
+template <int LANES>
+__device__ __forceinline__ uint32_t env_bcast(uint32_t v, int k)
+{
+    static_assert(LANES == 8 || LANES == 16, "row broadcasts serve 8 or 16 lanes per env");
+    uint32_t lo = 0u, hi = 0u;
+    switch (k) {
+#define HASE_BCAST(K)                                                                          \
+    case K:                                                                                    \
+        lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + (K), 0xF, 0xF, false);   \
+        if constexpr (LANES == 8)                                                              \
+            hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x158 + ((K) & 7), 0xF, 0xF, false); \
+        break;
+        HASE_BCAST(0) HASE_BCAST(1) HASE_BCAST(2) HASE_BCAST(3) HASE_BCAST(4) HASE_BCAST(5)
+        HASE_BCAST(6) HASE_BCAST(7) HASE_BCAST(8) HASE_BCAST(9) HASE_BCAST(10) HASE_BCAST(11)
+        HASE_BCAST(12) HASE_BCAST(13) HASE_BCAST(14) HASE_BCAST(15)
+#undef HASE_BCAST
+    default: break;
+    }
+    if constexpr (LANES == 8) return (threadIdx.x & 8u) ? hi : lo;
+    return lo;
+}
+
 template <int LANES>
 __device__ __forceinline__ uint64_t gather_window(uint32_t v)
 {
@@ -339,6 +364,8 @@ __device__ __forceinline__ void store_words(GAS uint32_t *p, const uint32_t (&v)
 // any window and never equal to a move target, so the inner loops need no
 // agent-count test.
 constexpr int FAR_CELL = (0xF0 << 8) | 0xF0;
+// a draw the agent may not take (above every packed cell)
+constexpr uint32_t NO_CELL = 0xffffu;
 
 // Move-target offsets of actions 0..4 (stay, N, S, E, W) as packed
 // (dy << 8) + dx + 257, 12 bits per action.
@@ -870,6 +897,10 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // for terrain, whose step loop then spilled more scalar registers and
     // ran 5% slower (terrain4k)
     constexpr bool LANE_SPAWN = !FAST_SPAWN && LANES >= 8 && (KIND & KIND_TERRAIN) == 0;
+    // moves with a lane per agent, 8 or 16 lanes per env and more than 4
+    // agents (no terrain): each lane decides its own agent's move (with two
+    // agents per lane, the 20-agent kernels spilled registers)
+    constexpr bool LANE_MOVES = LANES >= 8 && TPL == 1 && !NBR && (KIND & KIND_TERRAIN) == 0;
     constexpr int SL = NMAX >= 20 ? 2 : 3;
     static_assert(NMAX * SL <= 2 * MAX_AGENTS, "the draws fit the respawn words");
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
@@ -1304,6 +1335,43 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     const uint32_t blk = ((nbw >> (5u * (uint32_t)i + a)) & 1u) | (occ & cmask);
                     pp[i] = blk ? pp[i] : tg;
                 }
+            } else if constexpr (LANE_MOVES) {
+                // Each lane decides its own agents' moves. Agent i's target
+                // must be free of the cells of agents < i after their moves
+                // and of agents > i before theirs: the part over later agents
+                // is taken ahead in each lane; then, agent by agent in index
+                // order, the agent's lane decides, every lane of the env
+                // learns the new cell (a row broadcast from that lane) and
+                // tests its own targets against it (an agent that has decided
+                // no longer looks at its test, and agents past the last one
+                // decide nothing that counts). One board read per lane
+                // instead of one per agent, and no chain over all pairs in
+                // every lane.
+                int tg[TPL];
+                uint32_t wb[TPL], acc[TPL];
+#pragma unroll
+                for (int m = 0; m < TPL; ++m) {
+                    const int a = l + m * LANES;
+                    const uint32_t act = a < NMAX ? (uint32_t)(acts >> (3 * a)) & 7u : 0u;
+                    tg[m] = mine[m] + (int)((MOVE_TABLE >> (12u * act)) & 0x3ffull) - 257;
+                    uint32_t widx = (uint32_t)(tg[m] >> 8) * (uint32_t)LDS_ROW + (((uint32_t)tg[m] >> 5) & 7u);
+                    widx = widx < last_word ? widx : last_word;
+                    wb[m] = (slot[widx] >> ((uint32_t)tg[m] & 31u)) & 1u;
+                    uint32_t mn = 0xffffu;  // cells are below 2^16
+#pragma unroll
+                    for (int jj = 0; jj < NMAX; ++jj)
+                        mn = jj > a ? min(mn, (uint32_t)(tg[m] ^ pp[jj])) : mn;
+                    acc[m] = mn;
+                }
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    const int mi = i / LANES;
+                    const uint32_t blk = wb[mi] | (((acc[mi] - 1u) >> 31) & cmask);
+                    const int nc = (int)env_bcast<LANES>((uint32_t)(blk ? mine[mi] : tg[mi]), i % LANES);
+                    pp[i] = i < n ? nc : FAR_CELL;
+#pragma unroll
+                    for (int m = 0; m < TPL; ++m) acc[m] = min(acc[m], (uint32_t)(tg[m] ^ nc));
+                }
             } else {
                 // Board reads for every target first (one LDS round trip), then
                 // the sequential decisions with integer logic only. A target is
@@ -1566,70 +1634,48 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     }
                 }
                 if constexpr (LANE_SPAWN) {
-                    // The rule's first SL draws of every agent, made by the
-                    // lane of the agent's task, each kept (as its packed
-                    // cell) only if the agent may stand there, in the
-                    // 16-bit halves of the env's respawn words (agent a's
-                    // draw j in half a * SL + j). An agent takes its first
-                    // kept draw; that is the rule's choice whenever no
-                    // earlier agent kept the same cell among its draws
-                    // (its own choice is one of them). If some agent
-                    // kept none, or such a cell is shared, the rule runs
-                    // in full, from the first agent.
+                    // Each lane makes the rule's first SL draws of its own
+                    // agents and keeps those the agent may stand on (as
+                    // packed cells). Then, agent by agent in index order, the
+                    // agent's lane offers its first kept draw, every lane of
+                    // the env takes it (a broadcast from that lane) and drops
+                    // that cell from its own draws. This is the rule's choice
+                    // as long as each agent still has a kept draw; if one has
+                    // none left, the rule runs in full, from the first agent.
                     const uint32_t cells = (uint32_t)(H * Wd);
-                    uint16_t *cand = (uint16_t *)spawned;
+                    uint32_t dr[TPL][SL];
 #pragma unroll
                     for (int m = 0; m < TPL; ++m) {
                         const int a = l + m * LANES;
+                        // draws SL-1 down to 0, shifted in (one generator
+                        // block at a time: few registers)
 #pragma unroll 1
-                        for (int j = 0; j < SL; ++j) {
+                        for (int j = SL - 1; j >= 0; --j) {
                             const U4 x = philox(env, (ST_SPAWN << 24) | (uint32_t)a, ep, (uint32_t)j, k0, k1);
                             const uint32_t c = range_map(x.x, cells);
                             const uint32_t y = (c * wdiv) >> 18, xx = c - y * (uint32_t)Wd;
                             const int pc = (int)(((y + PAD) << 8) | (xx + PAD));
-                            const bool keep = a < n && may_stand(a, pc);
-                            if (a < NMAX) cand[a * SL + j] = (uint16_t)(keep ? pc : 0xffff);
+#pragma unroll
+                            for (int jj = SL - 1; jj > 0; --jj) dr[m][jj] = dr[m][jj - 1];
+                            dr[m][0] = (a < n && may_stand(a, pc)) ? (uint32_t)pc : NO_CELL;
                         }
                     }
-                    wave_lds_fence();
-                    uint32_t bad = 0u;
-                    int choice[TPL];
+                    uint32_t fail = 0u;
 #pragma unroll
-                    for (int m = 0; m < TPL; ++m) {
-                        const int a = l + m * LANES;
-                        uint32_t ch = 0xffffu;
+                    for (int a = 0; a < NMAX; ++a) {
+                        const int m = a / LANES;
+                        uint32_t f = dr[m][SL - 1];
 #pragma unroll
-                        for (int j = 0; j < SL; ++j) {
-                            const uint32_t v = a < NMAX ? cand[a * SL + j] : 0xffffu;
-                            ch = ch == 0xffffu ? v : ch;
-                        }
-                        // the draws of earlier agents, two per word (few
-                        // registers: this runs inside the step loop)
-                        uint32_t shared = 0u;
-                        const uint32_t *cw = (const uint32_t *)spawned;
-#pragma unroll 1
-                        for (int k = 0; 2 * k < a * SL; ++k) {
-                            const uint32_t w = cw[k];
-                            shared |= (w & 0xffffu) == ch ? 1u : 0u;
-                            shared |= (2 * k + 1 < a * SL && (w >> 16) == ch) ? 1u : 0u;
-                        }
-                        bad |= (a < n) ? (shared | (ch == 0xffffu ? 1u : 0u)) : 0u;
-                        choice[m] = (int)ch;
+                        for (int j = SL - 2; j >= 0; --j) f = dr[m][j] != NO_CELL ? dr[m][j] : f;
+                        const uint32_t ch = env_bcast<LANES>(f, a % LANES);
+                        fail |= (a < n && ch == NO_CELL) ? 1u : 0u;
+                        pp[a] = a < n ? (int)ch : FAR_CELL;
+#pragma unroll
+                        for (int m2 = 0; m2 < TPL; ++m2)
+#pragma unroll
+                            for (int j = 0; j < SL; ++j) dr[m2][j] = dr[m2][j] == ch ? NO_CELL : dr[m2][j];
                     }
-                    bad = group_or_dpp<LANES>(bad);
-                    // every read of the draws precedes the writes below
-                    wave_lds_fence();
-                    if (bad == 0u) {
-#pragma unroll
-                        for (int m = 0; m < TPL; ++m) {
-                            const int a = l + m * LANES;
-                            if (a < n) spawned[a] = choice[m];
-                        }
-                        wave_lds_fence();
-#pragma unroll
-                        for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
-                        by_rule = false;
-                    }
+                    by_rule = fail != 0u;
                 }
                 if (by_rule) {
                     spawn_agents_if(spawned, n, H, Wd, env, k0, k1, ep, may_stand);

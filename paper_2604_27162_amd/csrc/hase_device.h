@@ -901,6 +901,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // agents (no terrain): each lane decides its own agent's move (with two
     // agents per lane, the 20-agent kernels spilled registers)
     constexpr bool LANE_MOVES = LANES >= 8 && TPL == 1 && !NBR && (KIND & KIND_TERRAIN) == 0;
+    constexpr bool LANE_MOVES_T = LANES >= 8 && TPL == 1 && (KIND & KIND_TERRAIN) != 0;
     constexpr int SL = NMAX >= 20 ? 2 : 3;
     static_assert(NMAX * SL <= 2 * MAX_AGENTS, "the draws fit the respawn words");
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
@@ -1236,6 +1237,8 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 // words, and every lane runs the sequential occupancy chain
                 // (agents in index order) on them.
                 uint32_t *xw = (uint32_t *)spawned;
+                int own_tg = 0;
+                uint32_t own_go = 0u, own_st = 0u;
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) {
                     const int a = l + m * LANES;
@@ -1259,39 +1262,66 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     const uint32_t go = (chance(u, pct) ? 1u : 0u) & (blocked ^ 1u);
                     const uint32_t sticks = go & (cls == 0u ? 1u : 0u) & (type == 3u ? 1u : 0u) &
                                             (chance(v, (tch >> 16) & 0xffu) ? 1u : 0u);
-                    if (a < NMAX) xw[a] = (uint32_t)tg | (go << 16) | (sticks << 17);
+                    if constexpr (LANE_MOVES_T) {
+                        own_tg = tg;
+                        own_go = go;
+                        own_st = sticks;
+                    } else {
+                        if (a < NMAX) xw[a] = (uint32_t)tg | (go << 16) | (sticks << 17);
+                    }
                 }
-                wave_lds_fence();
-                int tgt[NMAX];
-                uint32_t gof[NMAX], stk[NMAX], mpre[NMAX];
+                if constexpr (LANE_MOVES_T) {
+                    // one agent per lane: the lane's agent is tested against
+                    // the old cells of later agents ahead, then agent by agent
+                    // the agent's lane decides and the env's lanes learn its
+                    // new cell and whether it got stuck (a row broadcast)
+                    uint32_t acc = 0xffffu;  // cells are below 2^16
 #pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    const uint32_t w = xw[i];
-                    tgt[i] = (int)(w & 0xffffu);
-                    gof[i] = (w >> 16) & 1u;
-                    stk[i] = (w >> 17) & 1u;
-                }
-                // the reads precede the radio exchange's and a respawn's
-                // writes to these words
-                wave_lds_fence();
-                // occupancy: the minimum of target ^ cell over the other
-                // agents is 0 exactly when the target is held; the part over
-                // agents that have not moved yet is taken ahead of the chain
+                    for (int jj = 0; jj < NMAX; ++jj)
+                        acc = jj > l ? min(acc, (uint32_t)(own_tg ^ pp[jj])) : acc;
 #pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    uint32_t mn = 0xffffu;  // cells are below 2^16
+                    for (int i = 0; i < NMAX; ++i) {
+                        const uint32_t moved = own_go & ~(((acc - 1u) >> 31) & cmask);
+                        const uint32_t w = env_bcast<LANES>(
+                            (uint32_t)(moved ? own_tg : mine[0]) | ((moved & own_st) << 16), i % LANES);
+                        const int nc = (int)(w & 0xffffu);
+                        pp[i] = i < n ? nc : FAR_CELL;
+                        stuck |= ((w >> 16) & 1u) << i;  // absent agents never move
+                        acc = min(acc, (uint32_t)(own_tg ^ nc));
+                    }
+                } else {
+                    wave_lds_fence();
+                    int tgt[NMAX];
+                    uint32_t gof[NMAX], stk[NMAX], mpre[NMAX];
 #pragma unroll
-                    for (int jj = i + 1; jj < NMAX; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
-                    mpre[i] = mn;
-                }
+                    for (int i = 0; i < NMAX; ++i) {
+                        const uint32_t w = xw[i];
+                        tgt[i] = (int)(w & 0xffffu);
+                        gof[i] = (w >> 16) & 1u;
+                        stk[i] = (w >> 17) & 1u;
+                    }
+                    // the reads precede the radio exchange's and a respawn's
+                    // writes to these words
+                    wave_lds_fence();
+                    // occupancy: the minimum of target ^ cell over the other
+                    // agents is 0 exactly when the target is held; the part over
+                    // agents that have not moved yet is taken ahead of the chain
 #pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    uint32_t mn = mpre[i];
+                    for (int i = 0; i < NMAX; ++i) {
+                        uint32_t mn = 0xffffu;  // cells are below 2^16
 #pragma unroll
-                    for (int jj = 0; jj < i; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
-                    const uint32_t moved = gof[i] & ~(((mn - 1u) >> 31) & cmask);
-                    stuck |= (moved & stk[i]) << i;
-                    pp[i] = moved ? tgt[i] : pp[i];
+                        for (int jj = i + 1; jj < NMAX; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
+                        mpre[i] = mn;
+                    }
+#pragma unroll
+                    for (int i = 0; i < NMAX; ++i) {
+                        uint32_t mn = mpre[i];
+#pragma unroll
+                        for (int jj = 0; jj < i; ++jj) mn = min(mn, (uint32_t)(tgt[i] ^ pp[jj]));
+                        const uint32_t moved = gof[i] & ~(((mn - 1u) >> 31) & cmask);
+                        stuck |= (moved & stk[i]) << i;
+                        pp[i] = moved ? tgt[i] : pp[i];
+                    }
                 }
                 // rescue: a stuck agent is freed by a teammate that is not
                 // stuck within Chebyshev distance 1 after the moves ((dy + 1)

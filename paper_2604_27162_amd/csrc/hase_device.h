@@ -893,17 +893,14 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     constexpr bool FAST_SPAWN = DPP_WINDOW && (KIND & KIND_TERRAIN) == 0 && LANES >= NMAX;
     constexpr int SA = FAST_SPAWN ? LANES / NMAX : 1;
     // with 8 or 16 lanes per env each lane draws the first SL draws of its
-    // own agents (the env's respawn words hold NMAX * SL 16-bit cells); not
-    // for terrain, whose step loop then spilled more scalar registers and
-    // ran 5% slower (terrain4k)
-    constexpr bool LANE_SPAWN = !FAST_SPAWN && LANES >= 8 && (KIND & KIND_TERRAIN) == 0;
+    // own agents
+    constexpr bool LANE_SPAWN = !FAST_SPAWN && LANES >= 8;
     // moves with a lane per agent, 8 or 16 lanes per env and more than 4
     // agents (no terrain): each lane decides its own agent's move (with two
     // agents per lane, the 20-agent kernels spilled registers)
     constexpr bool LANE_MOVES = LANES >= 8 && TPL == 1 && !NBR && (KIND & KIND_TERRAIN) == 0;
     constexpr bool LANE_MOVES_T = LANES >= 8 && TPL == 1 && (KIND & KIND_TERRAIN) != 0;
     constexpr int SL = NMAX >= 20 ? 2 : 3;
-    static_assert(NMAX * SL <= 2 * MAX_AGENTS, "the draws fit the respawn words");
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
 
     const int lane = (int)threadIdx.x;

@@ -249,6 +249,8 @@ def main():
                     help="choose the tiling with the autotuner (timed runs of STEPS steps)")
     ap.add_argument("--only-runs", action="store_true",
                     help="time the runs only (profiling: no other launch of the step kernel)")
+    ap.add_argument("--only-per-launch", action="store_true",
+                    help="time only the run with one kernel launch per env-step (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-maps", action="store_true",
                     help="exploring workloads: skip the per-step discovery-map output")
@@ -298,6 +300,21 @@ def main():
     obs, rew, done = g.alloc_outputs(R)
     mp = g.alloc_outputs(R, maps=True)[3] if maps_on else None
     st = g.alloc_state_outputs(R) if state_on else None
+    if args.only_per_launch:
+        # one kernel launch per env-step only: P launches after a 50-launch warm-up
+        P = min(R, 2000)
+        g.step_into(obs, rew, done, min(P, 50), mode=hase.PER_LAUNCH, maps=mp, state=st)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step_into(obs, rew, done, P, mode=hase.PER_LAUNCH, maps=mp, state=st)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_pl = e0.elapsed_time(e1)
+        print(json.dumps({"per_launch_env_steps": P, "ms_per_env_step": ms_pl / P,
+                          "workload": args.workload}), flush=True)
+        g.close()
+        return
     g.prepare(obs, rew, done, R, maps=mp, state=st)
     for _ in range(W):
         g.step_into(obs, rew, done, R, maps=mp, state=st)

@@ -356,8 +356,9 @@ int hase_get_tiling(const hase_batch *b, uint32_t lanes[HASE_N_BUCKETS]);
 /*
  * Autotuner of the tiling: coordinate descent over lanes_per_env of every
  * agent-count bucket present in the batch, timing persistent calls of
- * n_steps (HIP events on the handle's stream) into the caller's scratch
- * outputs (sized as for hase_step with n_steps). The state is snapshotted
+ * n_steps (HIP events on the handle's stream; the median of 5 runs per
+ * candidate, which replaces the best only when more than 2% faster) into the
+ * caller's scratch outputs (sized as for hase_step with n_steps). The state is snapshotted
  * and restored, so tuning does not advance the envs, and results never depend
  * on the tiling. Applies the fastest tiling found and copies it to lanes_out
  * (may be NULL). Synchronises the stream.

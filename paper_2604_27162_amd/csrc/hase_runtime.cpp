@@ -662,6 +662,9 @@ int snapshot_restore(hase_batch *b, const Snapshot &s)
 // Milliseconds of a persistent call of n_steps under the current tiling: the
 // faster of two timed calls, after an untimed one that also captures the
 // graph; the state is restored before each call and at the end.
+constexpr int AUTOTUNE_REPS = 5;
+constexpr float AUTOTUNE_MARGIN = 0.02f;
+
 int time_tiling(hase_batch *b, const JobDesc &job, uint32_t n_steps, const Snapshot &snap,
                 float *ms)
 {
@@ -671,18 +674,21 @@ int time_tiling(hase_batch *b, const JobDesc &job, uint32_t n_steps, const Snaps
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     hipError_t err = hipSuccess;
-    *ms = 0.f;
-    for (int rep = 0; rep < 2 && !rc && err == hipSuccess; ++rep) {
+    // the median of AUTOTUNE_REPS timed runs, each from the same snapshot
+    float t[AUTOTUNE_REPS] = {};
+    int got = 0;
+    for (int rep = 0; rep < AUTOTUNE_REPS && !rc && err == hipSuccess; ++rep) {
         rc = snapshot_restore(b, snap);
         if (rc) break;
         err = hipEventRecord(e0, b->stream);
         if (err == hipSuccess) rc = persistent_step(b, job, n_steps);
         if (err == hipSuccess && !rc) err = hipEventRecord(e1, b->stream);
         if (err == hipSuccess && !rc) err = hipEventSynchronize(e1);
-        float t = 0.f;
-        if (err == hipSuccess && !rc) err = hipEventElapsedTime(&t, e0, e1);
-        if (err == hipSuccess && !rc) *ms = rep == 0 ? t : std::min(*ms, t);
+        if (err == hipSuccess && !rc) err = hipEventElapsedTime(&t[got], e0, e1);
+        if (err == hipSuccess && !rc) ++got;
     }
+    std::sort(t, t + got);
+    *ms = got ? t[got / 2] : 0.f;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
@@ -1077,7 +1083,9 @@ int hase_autotune(hase_batch *b, uint32_t n_steps, uint32_t *d_obs, float *d_rew
             float ms = 0.f;
             rc = time_tiling(b, job, n_steps, snap, &ms);
             if (rc) break;
-            if (ms < best_ms) {
+            // a candidate must beat the best by more than the run-to-run
+            // spread of the median
+            if (ms < best_ms * (1.f - AUTOTUNE_MARGIN)) {
                 best_ms = ms;
                 best[bk] = L;
             }

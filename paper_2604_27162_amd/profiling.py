@@ -18,6 +18,11 @@ summary (--summarize-only can redo it from raw output copied back from the
 GPU machine) to profiles/step_kernel_<workload>.md and the HBM traffic per
 launch to profiles/traffic.json, keyed by the hash of the device sources so
 that bench.py reports it only while the kernel is unchanged.
+
+With --per-launch, one kernel trace of bench.py --only-per-launch (one
+launch per env-step) instead, summarised to
+profiles/step_kernel_<workload>_per_launch.md: kernel time per launch
+against the gaps between launches.
 """
 from __future__ import annotations
 
@@ -70,7 +75,12 @@ def main(argv=None):
     ap.add_argument("--collect-only", action="store_true", help="run rocprofv3 only")
     ap.add_argument("--summarize-only", action="store_true",
                     help="only summarise raw output collected earlier")
+    ap.add_argument("--per-launch", action="store_true",
+                    help="profile the run with one kernel launch per env-step instead "
+                         "(kernel trace only)")
     args = ap.parse_args(argv)
+    if args.per_launch:
+        return per_launch(args)
     raw = os.path.abspath(args.raw or os.path.join(ROOT, "rocprof_raw", f"profile_{args.workload}"))
     os.makedirs(raw, exist_ok=True)
     os.makedirs(args.out, exist_ok=True)
@@ -171,6 +181,54 @@ def main(argv=None):
         f.write("| counter | total | per wave | per wave-step |\n|---|---|---|---|\n")
         for c in SQ:
             f.write(f"| {c} | {sq[c]:.4e} | {sq[c] / waves:.1f} | {sq[c] / waves / steps:.2f} |\n")
+    print(open(md).read())
+
+
+def per_launch(args):
+    """Kernel trace of bench.py --only-per-launch: how the time of one env-step
+    launched on its own splits into kernel time and the gaps between
+    launches. Written to profiles/step_kernel_<workload>_per_launch.md."""
+    raw = os.path.abspath(args.raw or os.path.join(ROOT, "rocprof_raw", f"per_launch_{args.workload}"))
+    os.makedirs(raw, exist_ok=True)
+    os.makedirs(args.out, exist_ok=True)
+    py = sys.executable
+    cmd = ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv", "-d", f"{raw}/trace",
+           "-o", "run", "--", py, os.path.join(ROOT, "bench.py"), "--workload", args.workload,
+           "--only-per-launch", "--no-cpu-baseline"]
+    log = f"{raw}/trace.log"
+    if not args.summarize_only:
+        _run(cmd, log, timeout=170)
+    timed = None
+    for line in open(log):
+        if line.startswith("{") and "ms_per_env_step" in line:
+            timed = json.loads(line)
+    disp = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                  for r in _csv(f"{raw}/trace/*kernel_trace.csv") if "step_kernel" in r["Kernel_Name"])
+    # the timed launches are the last P dispatches
+    P = timed["per_launch_env_steps"] if timed else len(disp)
+    disp = disp[-P:]
+    dur = sorted(e - b for b, e in disp)
+    gaps = sorted(disp[i + 1][0] - disp[i][1] for i in range(len(disp) - 1))
+    med = lambda v: v[len(v) // 2] if v else 0.0
+    sys.path.insert(0, ROOT)
+    import bench
+    khash = bench.kernel_source_hash()
+    span_us = (disp[-1][1] - disp[0][0]) / 1e3 / len(disp) if disp else 0.0
+    md = os.path.join(args.out, f"step_kernel_{args.workload}_per_launch.md")
+    with open(md, "w") as f:
+        f.write(f"# step kernel, workload {args.workload}, one launch per env-step\n\n")
+        f.write(f"Device sources hash: `{khash}`\n\n")
+        rel = [c.replace(ROOT + "/", "").replace(raw, "<raw>").replace(py, "python3") for c in cmd]
+        f.write(f"Command (run from /tmp): `{' '.join(rel)}`\n\n")
+        f.write(f"- timed launches: {len(disp)} (after a 50-launch warm-up)\n")
+        f.write(f"- kernel duration per launch: median {med(dur) / 1e3:.3f} us, min "
+                f"{dur[0] / 1e3:.3f} us, max {dur[-1] / 1e3:.3f} us\n")
+        f.write(f"- gap between consecutive launches: median {med(gaps) / 1e3:.3f} us, min "
+                f"{gaps[0] / 1e3:.3f} us\n")
+        f.write(f"- first start to last end per launch: {span_us:.3f} us\n")
+        if timed:
+            f.write(f"- bench.py's timed figure (events around the {P} launches): "
+                    f"{timed['ms_per_env_step'] * 1e3:.3f} us per env-step\n")
     print(open(md).read())
 
 

@@ -252,6 +252,39 @@ __device__ __forceinline__ void window_rows(const uint32_t *slot, int H, int Wd,
     }
 }
 
+// Windows of radius R over the env's two agent planes (seekers at pl, hiders
+// pw words later; the board's padded row layout, no bits outside the map):
+// bit k = row * D + column, as for the walls.
+template <int R, int W>
+__device__ __forceinline__ void plane_windows(const uint32_t *pl, int pw, int ax, int ay,
+                                              uint32_t (&sk)[W], uint32_t (&hd)[W])
+{
+    constexpr int D = 2 * R + 1;
+    constexpr uint32_t DM = (1u << D) - 1u;
+    const int col = ax - R;
+    const uint32_t *base = pl + (ay - R) * LDS_ROW + (col >> 5);
+    const uint32_t sh = (uint32_t)(col & 31);
+#pragma unroll
+    for (int i = 0; i < W; ++i) sk[i] = hd[i] = 0u;
+#pragma unroll
+    for (int rho = 0; rho < D; ++rho) {
+        const uint32_t *rp = base + rho * LDS_ROW;
+        const uint32_t s = __builtin_amdgcn_alignbit(rp[1], rp[0], sh) & DM;
+        const uint32_t h = __builtin_amdgcn_alignbit(rp[pw + 1], rp[pw], sh) & DM;
+        const int off = rho * D, wi = off >> 5, b = off & 31;
+        sk[wi] |= s << b;
+        hd[wi] |= h << b;
+        if (b + D > 32) {
+            sk[wi + 1] |= s >> (32 - b);
+            hd[wi + 1] |= h >> (32 - b);
+        }
+    }
+}
+
+// Word and bit of packed padded cell pc in a plane of the board's layout.
+__device__ __forceinline__ uint32_t plane_word(int pc) { return (uint32_t)((pc >> 8) * LDS_ROW + ((pc & 0xff) >> 5)); }
+__device__ __forceinline__ uint32_t plane_bit(int pc) { return 1u << (pc & 31); }
+
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t v)
 {
@@ -379,12 +412,13 @@ constexpr uint64_t MOVE_TABLE = 0x101ull | (0x001ull << 12) | (0x201ull << 24) |
 // only agent on the centre cell is the agent itself. exact == true tests
 // every other agent by index. Returns the number of other-role agents in the
 // window (Chebyshev distance <= R).
-template <int R, int W, int NMAX, bool EXACT, bool TER = false>
+template <int R, int W, int NMAX, bool EXACT, bool TER = false, bool PLN = false>
 __device__ __forceinline__ int agent_masks_raw(const uint32_t *slot, int H, int Wd,
                                            const int (&pp)[NMAX], int a, int pa, int n, int S,
                                            bool want_out, uint32_t (&wall)[W], uint32_t (&outm)[W],
                                            uint32_t (&team)[W], uint32_t (&opp)[W], int pw = 0,
-                                           uint32_t cls = 0u, uint32_t (*lw)[W] = nullptr)
+                                           uint32_t cls = 0u, uint32_t (*lw)[W] = nullptr,
+                                           const uint32_t *planes = nullptr, int plw = 0)
 {
     constexpr int D = 2 * R + 1;
     constexpr int CENTER = R * D + R;
@@ -439,6 +473,22 @@ __device__ __forceinline__ int agent_masks_raw(const uint32_t *slot, int H, int 
             team[2] = tm_hi;
             opp[2] = op_hi;
         }
+        return cnt;
+    } else if constexpr (!EXACT && PLN) {
+        // Distinct cells, one agent per lane: the env's seeker and hider
+        // planes (kept up to date by the agents' own lanes) read like the
+        // walls; the agent's own bit is the centre of its own role's window.
+        uint32_t skw[W], hdw[W];
+        plane_windows<R, W>(planes, plw, pa & 0xff, pa >> 8, skw, hdw);
+        const bool sa = a < S;
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            team[i] = sa ? skw[i] : hdw[i];
+            opp[i] = sa ? hdw[i] : skw[i];
+            cnt += __builtin_popcount(opp[i]);
+        }
+        team[CENTER >> 5] &= ~(1u << (CENTER & 31));
         return cnt;
     } else if constexpr (!EXACT) {
         // Bits of all agents in the window, and of the seekers among them,
@@ -664,23 +714,24 @@ __device__ __forceinline__ int occlude(const int (&pp)[NMAX], int a, int pa, int
 // the visible cells and the opponent count to visible opponents; with
 // exploration (xpl) seen gets the window cells that are visible and inside
 // the map (bits past the window's D*D cells are undefined).
-template <int R, int W, int NMAX, bool EXACT, bool FEAT, bool TER>
+template <int R, int W, int NMAX, bool EXACT, bool FEAT, bool TER, bool PLN = false>
 __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
                                            const int (&pp)[NMAX], int a, int pa, int n, int S,
                                            bool want_out, bool occl, bool xpl, uint32_t (&wall)[W],
                                            uint32_t (&outm)[W], uint32_t (&team)[W],
                                            uint32_t (&opp)[W], uint32_t (&seen)[W], int pw,
-                                           uint32_t cls)
+                                           uint32_t cls, const uint32_t *planes = nullptr,
+                                           int plw = 0)
 {
     // exploration needs the outside-the-map cells whatever the channel count
     // (outm is stored only for 4-channel envs); with terrain and line of
     // sight, only walls and outside block sight, not what the class may not
     // enter
     uint32_t lw[W];
-    int cnt = agent_masks_raw<R, W, NMAX, EXACT, TER>(slot, H, Wd, pp, a, pa, n, S,
-                                                      FEAT ? (want_out || xpl) : want_out, wall,
-                                                      outm, team, opp, pw, cls,
-                                                      (TER && occl) ? &lw : nullptr);
+    int cnt = agent_masks_raw<R, W, NMAX, EXACT, TER, PLN>(slot, H, Wd, pp, a, pa, n, S,
+                                                           FEAT ? (want_out || xpl) : want_out, wall,
+                                                           outm, team, opp, pw, cls,
+                                                           (TER && occl) ? &lw : nullptr, planes, plw);
     if constexpr (FEAT) {
         uint32_t vis[W];
 #pragma unroll
@@ -697,7 +748,7 @@ __device__ __forceinline__ int agent_masks(const uint32_t *slot, int H, int Wd,
     return cnt;
 }
 
-template <int R, int W, int NMAX, int TPL, bool EXACT, bool FEAT, bool TER = false>
+template <int R, int W, int NMAX, int TPL, bool EXACT, bool FEAT, bool TER = false, bool PLN = false>
 __device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
                                           const int (&pp)[NMAX], int l, int lanes,
                                           const int (&mine)[TPL], int n, int S, bool want_out,
@@ -705,15 +756,16 @@ __device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
                                           uint32_t (&outm)[TPL][W], uint32_t (&team)[TPL][W],
                                           uint32_t (&opp)[TPL][W], uint32_t (&seen)[TPL][W],
                                           int (&cnt)[TPL], int pw = 0, uint32_t clo = 0u,
-                                          uint32_t chi = 0u)
+                                          uint32_t chi = 0u, const uint32_t *planes = nullptr,
+                                          int plw = 0)
 {
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
         const int a = l + m * lanes;
         const uint32_t cls = TER ? agent_class(clo, chi, a) : 0u;
-        cnt[m] = agent_masks<R, W, NMAX, EXACT, FEAT, TER>(slot, H, Wd, pp, a, mine[m], n, S,
-                                                           want_out, occl, xpl, wall[m], outm[m],
-                                                           team[m], opp[m], seen[m], pw, cls);
+        cnt[m] = agent_masks<R, W, NMAX, EXACT, FEAT, TER, PLN>(
+            slot, H, Wd, pp, a, mine[m], n, S, want_out, occl, xpl, wall[m], outm[m], team[m],
+            opp[m], seen[m], pw, cls, planes, plw);
     }
 }
 
@@ -900,6 +952,12 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // agents per lane, the 20-agent kernels spilled registers)
     constexpr bool LANE_MOVES = LANES >= 8 && TPL == 1 && !NBR && (KIND & KIND_TERRAIN) == 0;
     constexpr bool LANE_MOVES_T = LANES >= 8 && TPL == 1 && (KIND & KIND_TERRAIN) != 0;
+    // one agent per lane and more than 4 agents: the teammate / opponent
+    // channels of envs with distinct cells come from two LDS planes of the
+    // agents' cells (seekers, hiders), each lane keeping its own agent's bit
+    // up to date, instead of a pass over all agents per lane (not for
+    // terrain, which ran 7% slower with them)
+    constexpr bool PLANES = LANES >= 8 && TPL == 1 && NMAX > 4 && (KIND & KIND_TERRAIN) == 0;
     constexpr int SL = NMAX >= 20 ? 2 : 3;
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
 
@@ -969,9 +1027,12 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // this env's LDS slot: the padded bitboard, then MAX_AGENTS words where a
     // respawn writes the new positions, then (feature launches with an
     // exploring env) the discovery map
-    uint32_t *slot = lds + (uint32_t)q * (slot_words + MAX_AGENTS + map_words);
+    uint32_t *slot = lds + (uint32_t)q * (slot_words * (PLANES ? 3u : 1u) + MAX_AGENTS + map_words);
     int *spawned = (int *)(slot + slot_words);
     uint32_t *mslot = slot + slot_words + MAX_AGENTS;
+    // the agent planes (PLANES): seekers, then hiders slot_words later
+    uint32_t *planes = slot + slot_words + MAX_AGENTS + map_words;
+    const int plw = (int)slot_words;
     const uint32_t map_off = XPL ? gp(J.tab.map_off)[e] : 0u;
     if constexpr (XPL) {
         if (K != 0u) map_load<LANES>(mslot, gp(J.disc) + map_off, H, Wd, l);
@@ -1015,6 +1076,14 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // lanes without an agent), kept in registers
     int mine[TPL];
     own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+    if constexpr (PLANES) {
+        for (uint32_t i = (uint32_t)l; i < 2u * slot_words; i += LANES) planes[i] = 0u;
+        wave_lds_fence();
+        if (l < n)
+            __hip_atomic_fetch_or(planes + (l < S ? 0 : plw) + plane_word(mine[0]), plane_bit(mine[0]),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        wave_lds_fence();
+    }
 
     const uint32_t hmask = (uint32_t)(((1ull << n) - 1ull) & ~((1ull << S) - 1ull));
     const uint64_t amask = (1ull << (3 * n)) - 1ull;  // action bits of real agents
@@ -1121,6 +1190,21 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         constexpr bool LOS = (FK & KIND_LOS) != 0;
         constexpr bool XP = (FK & KIND_EXPLORE) != 0;
         constexpr bool USE_PAIRS = PAIRS && !LOS;
+        constexpr bool PL = PLANES && !EX;
+        // the lane's agent moves from cell `from` to cell `to` in the planes
+        // (every clear of the wave comes before every set)
+        auto plane_move = [&](int from, int to) __attribute__((always_inline)) {
+            if constexpr (PL) {
+                uint32_t *pl = planes + (l < S ? 0 : plw);
+                if (l < n) {
+                    __hip_atomic_fetch_and(pl + plane_word(from), ~plane_bit(from), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_or(pl + plane_word(to), plane_bit(to), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                wave_lds_fence();
+            }
+        };
         uint32_t wall[TPL][W], outm[TPL][W], team[TPL][W], opp[TPL][W], seen[TPL][W];
         int cnt[TPL];
 
@@ -1143,9 +1227,9 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         };
 
         if (obs_only) {
-            all_masks<R, W, NMAX, TPL, EX, OC, TER>(slot, H, Wd, pp, l, LANES, mine, n, S,
-                                                    want_out, LOS, false, wall, outm, team, opp,
-                                                    seen, cnt, pw, clo, chi);
+            all_masks<R, W, NMAX, TPL, EX, OC, TER, PL>(slot, H, Wd, pp, l, LANES, mine, n, S,
+                                                        want_out, LOS, false, wall, outm, team,
+                                                        opp, seen, cnt, pw, clo, chi, planes, plw);
 #pragma unroll
             for (int m = 0; m < TPL; ++m)
                 if (mine_live[m]) store_obs(m);
@@ -1220,6 +1304,8 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             }
             acts &= amask;
 
+            // the lane's agent's cell before the moves (for the planes)
+            const int pl_from = mine[0];
             // ---- 2 moves, agent-index order (redundant in every lane of the env)
             if constexpr (TER) {
                 // Terrain: a stuck agent stays; the target must be a tile the
@@ -1430,11 +1516,12 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 }
             }
             own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+            plane_move(pl_from, mine[0]);
 
             // ---- 3 detection at the post-move positions, and the channels
-            all_masks<R, W, NMAX, TPL, EX, OC, TER>(slot, H, Wd, pp, l, LANES, mine, n, S,
-                                                    want_out, LOS, XP, wall, outm, team, opp,
-                                                    seen, cnt, pw, clo, chi);
+            all_masks<R, W, NMAX, TPL, EX, OC, TER, PL>(slot, H, Wd, pp, l, LANES, mine, n, S,
+                                                        want_out, LOS, XP, wall, outm, team, opp,
+                                                        seen, cnt, pw, clo, chi, planes, plw);
             // The role channels feed only the (predicated) stores, so the
             // compiler would compute them inside the store region; using them
             // here keeps them in the step's main block, where they fill the
@@ -1710,10 +1797,14 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
 #pragma unroll
                     for (int jj = 0; jj < NMAX; ++jj) pp[jj] = jj < n ? spawned[jj] : FAR_CELL;
                 }
-                own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
-                all_masks<R, W, NMAX, TPL, EX, OC, TER>(slot, H, Wd, pp, l, LANES, mine, n, S,
-                                                        want_out, LOS, false, wall, outm, team,
-                                                        opp, seen, cnt, pw, clo, chi);
+                {
+                    const int from = mine[0];
+                    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+                    plane_move(from, mine[0]);
+                }
+                all_masks<R, W, NMAX, TPL, EX, OC, TER, PL>(slot, H, Wd, pp, l, LANES, mine, n, S,
+                                                            want_out, LOS, false, wall, outm, team,
+                                                            opp, seen, cnt, pw, clo, chi, planes, plw);
 #pragma unroll
                 for (int m = 0; m < TPL; ++m)
                     if (mine_live[m]) store_obs(m);
@@ -2095,7 +2186,11 @@ inline hipError_t launch_variant(const Tile *tiles, uint32_t n_tiles, const JobD
                                  const JobDesc &job0, uint32_t K, uint32_t step_base,
                                  uint32_t slot_words, hipStream_t stream)
 {
-    const size_t lds = (size_t)(64 / LANES) * (slot_words + MAX_AGENTS) * sizeof(uint32_t);
+    // env slots with the two agent planes where one lane holds one of more
+    // than 4 agents
+    constexpr bool planes = LANES >= 8 && NMAX > 4 && NMAX <= LANES;
+    const size_t lds =
+        (size_t)(64 / LANES) * (slot_words * (planes ? 3u : 1u) + MAX_AGENTS) * sizeof(uint32_t);
     hipLaunchKernelGGL((step_kernel<LANES, NMAX, R>), dim3(n_tiles), dim3(64), lds, stream, tiles,
                        n_tiles, jobs, job0, K, step_base, slot_words);
     return hipGetLastError();
@@ -2139,8 +2234,12 @@ inline hipError_t launch_mixed_l(const Tile *tiles, uint32_t n_tiles, const JobD
                                  uint32_t slot_words, uint32_t map_words, bool big,
                                  hipStream_t stream)
 {
-    const size_t lds =
-        (size_t)(64 / LANES) * (slot_words + MAX_AGENTS + map_words) * sizeof(uint32_t);
+    // the 16-lane kernels without terrain hold the bucket of up to 10
+    // agents, whose env slots carry the two agent planes
+    constexpr bool planes = LANES >= 16 && (KIND & KIND_TERRAIN) == 0;
+    const size_t lds = (size_t)(64 / LANES) *
+                       (slot_words * (planes ? 3u : 1u) + MAX_AGENTS + map_words) *
+                       sizeof(uint32_t);
     if (big)
         hipLaunchKernelGGL((step_kernel_mixed<LANES, KIND, true>), dim3(n_tiles), dim3(64), lds,
                            stream, tiles, n_tiles, jobs, job0, K, step_base, slot_words, map_words);

@@ -930,10 +930,13 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // with at most 4 agents and 2 or 4 lanes the window is gathered by DPP and
     // spans exactly LANES steps
     constexpr bool DPP_WINDOW = WINDOWED && NMAX <= 4 && (LANES == 2 || LANES == 4);
-    // external actions of windowed loops (without radio, whose targets come
-    // with the action bytes) are read a window ahead and merged into the
-    // window's generator blocks, so no step waits for its action bytes
-    constexpr bool WIN_ACT = WINDOWED && (KIND & KIND_RADIO) == 0;
+    // external actions of windowed loops are read a window ahead and merged
+    // into the window's generator blocks, so no step waits for its action
+    // bytes; radio targets come with the bytes, so radio envs do this only
+    // where their targets are drawn for a window too (more than 2 or 4
+    // lanes' DPP windows)
+    constexpr bool WIN_ACT =
+        WINDOWED && ((KIND & KIND_RADIO) == 0 || !(NMAX <= 4 && (LANES == 2 || LANES == 4)));
     // with at most 4 agents the wall tests of the moves come from bits kept
     // from the previous step's windows instead of board reads, and detection
     // (rewards, found bits) is a pairwise Chebyshev test in every lane of the
@@ -1272,7 +1275,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                                                 pick((a & 1u) != 0u, x.y, x.x));
                         tgt_r[m] = range_map(w, (uint32_t)n);
                     }
-                    if (has_act && (int)a < n) {
+                    if (has_act && !WIN_ACT && (int)a < n) {
                         const int v = act_p[a];
                         if (v != -1) {
                             // v >= 0: target v div 5 - 1 (0 or past the last agent: none)
@@ -1886,15 +1889,33 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             return x;
         };
         // a generator block's four 3-bit actions with the external bytes
-        // merged in (-1 keeps the draw, 0..4 replaces it, anything else stays)
+        // merged in (-1 keeps the draw, 0..4 replaces it, anything else stays;
+        // with radio v >= 0 moves v mod 5)
         auto merge_ext = [&](uint32_t drawn, const ExtBytes &x) __attribute__((always_inline)) {
             if (!has_act) return drawn;
             const uint32_t bytes = (x.b[0] | (x.b[1] << 8) | (x.b[2] << 16) | (x.b[3] << 24)) | x.draw;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int v = (int)(int8_t)(bytes >> (8 * i));
-                const uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                uint32_t a = (v >= 0 && v <= 4) ? (uint32_t)v : 0u;
+                if constexpr (RAD) a = v >= 0 ? (uint32_t)v % 5u : 0u;
                 drawn = v == -1 ? drawn : ((drawn & ~(7u << (3 * i))) | (a << (3 * i)));
+            }
+            return drawn;
+        };
+        // a radio block's four 5-bit targets (agents 4g .. 4g+3) with the
+        // external bytes merged in: v >= 0 names agent v div 5 - 1 (0 or
+        // past the last agent: no message, the agent's own index), -1
+        // keeps the draw, anything else sends nothing
+        auto merge_tgt = [&](uint32_t drawn, const ExtBytes &x, uint32_t g) __attribute__((always_inline)) {
+            if (!has_act) return drawn;
+            const uint32_t bytes = (x.b[0] | (x.b[1] << 8) | (x.b[2] << 16) | (x.b[3] << 24)) | x.draw;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = (int)(int8_t)(bytes >> (8 * i));
+                const uint32_t c = v >= 0 ? (uint32_t)v / 5u : 0u;
+                const uint32_t t = (c >= 1u && c <= (uint32_t)n) ? c - 1u : 4u * g + (uint32_t)i;
+                drawn = v == -1 ? drawn : ((drawn & ~(31u << (5 * i))) | (t << (5 * i)));
             }
             return drawn;
         };
@@ -1989,31 +2010,48 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 j = (j + 1 == kb) ? 0 : j + 1;
             }
         } else if constexpr (WINDOWED) {
-            // the same, one window of kb steps per outer iteration
-            ExtBytes nb = ext_bytes((uint32_t)wstep, (uint32_t)wgroup);
-            for (uint32_t left = nsteps; left != 0u;) {
-                const ExtBytes cb = nb;
-                nb = ext_bytes(nsteps - left + (uint32_t)kb + (uint32_t)wstep, (uint32_t)wgroup);
-                const uint32_t drawn = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
-                const uint32_t win = WIN_ACT ? merge_ext(drawn, cb) : drawn;
-                if constexpr (RWIN) rwin = block_targets((uint32_t)wgroup, steps + (uint32_t)wstep);
-                const uint32_t nw = left < (uint32_t)kb ? left : (uint32_t)kb;
-#pragma unroll 1
-                for (uint32_t j = 0; j < nw; ++j) {
-                    if constexpr (RWIN) rj = j;
-                    uint64_t acts = 0;
-#pragma unroll
-                    for (int g = 0; g < MAXCALLS; ++g) {
-                        if (g < ncalls) {
-                            const uint32_t v =
-                                (uint32_t)__shfl((int)win, q * LANES + (int)j * ncalls + g, 64);
-                            acts |= (uint64_t)v << (12 * g);
-                        }
+            // the same, one window of kb steps per outer iteration; compiled
+            // twice, with and without external actions (a run-time test
+            // around the byte loads makes the compiler wait for every
+            // outstanding store where the paths join)
+            auto feature_loop = [&](auto with_act) __attribute__((always_inline)) {
+                constexpr bool WA = decltype(with_act)::value && WIN_ACT;
+                ExtBytes nb{};
+                if constexpr (WA) nb = ext_bytes((uint32_t)wstep, (uint32_t)wgroup);
+                for (uint32_t left = nsteps; left != 0u;) {
+                    const ExtBytes cb = nb;
+                    const uint32_t drawn = block_actions((uint32_t)wgroup, steps + (uint32_t)wstep);
+                    uint32_t win = drawn;
+                    if constexpr (WA) {
+                        nb = ext_bytes(nsteps - left + (uint32_t)kb + (uint32_t)wstep, (uint32_t)wgroup);
+                        win = merge_ext(drawn, cb);
                     }
-                    step(acts);
+                    if constexpr (RWIN) {
+                        rwin = block_targets((uint32_t)wgroup, steps + (uint32_t)wstep);
+                        if constexpr (WA) rwin = merge_tgt(rwin, cb, (uint32_t)wgroup);
+                    }
+                    const uint32_t nw = left < (uint32_t)kb ? left : (uint32_t)kb;
+#pragma unroll 1
+                    for (uint32_t j = 0; j < nw; ++j) {
+                        if constexpr (RWIN) rj = j;
+                        uint64_t acts = 0;
+#pragma unroll
+                        for (int g = 0; g < MAXCALLS; ++g) {
+                            if (g < ncalls) {
+                                const uint32_t v =
+                                    (uint32_t)__shfl((int)win, q * LANES + (int)j * ncalls + g, 64);
+                                acts |= (uint64_t)v << (12 * g);
+                            }
+                        }
+                        step(acts);
+                    }
+                    left -= nw;
                 }
-                left -= nw;
-            }
+            };
+            if (has_act)
+                feature_loop(std::true_type{});
+            else
+                feature_loop(std::false_type{});
         } else {
             for (uint32_t k = 0; k < nsteps; ++k) {
                 uint64_t acts = 0;

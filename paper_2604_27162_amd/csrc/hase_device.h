@@ -370,6 +370,20 @@ __device__ __forceinline__ void own_positions(const int (&pp)[NMAX], int l, int 
     }
 }
 
+// Positions of the agents whose indices a lane's tasks hold (aid[m] < n).
+template <int NMAX, int TPL>
+__device__ __forceinline__ void own_positions_ids(const int (&pp)[NMAX], const int (&aid)[TPL],
+                                                  int (&mine)[TPL])
+{
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+        int v = pp[0];
+#pragma unroll
+        for (int i = 1; i < NMAX; ++i) v = (aid[m] == i) ? pp[i] : v;
+        mine[m] = v;
+    }
+}
+
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 
@@ -757,11 +771,11 @@ __device__ __forceinline__ void all_masks(const uint32_t *slot, int H, int Wd,
                                           uint32_t (&opp)[TPL][W], uint32_t (&seen)[TPL][W],
                                           int (&cnt)[TPL], int pw = 0, uint32_t clo = 0u,
                                           uint32_t chi = 0u, const uint32_t *planes = nullptr,
-                                          int plw = 0)
+                                          int plw = 0, const int *aids = nullptr)
 {
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
-        const int a = l + m * lanes;
+        const int a = aids != nullptr ? aids[m] : l + m * lanes;
         const uint32_t cls = TER ? agent_class(clo, chi, a) : 0u;
         cnt[m] = agent_masks<R, W, NMAX, EXACT, FEAT, TER, PLN>(
             slot, H, Wd, pp, a, mine[m], n, S, want_out, occl, xpl, wall[m], outm[m], team[m],
@@ -961,6 +975,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // up to date, instead of a pass over all agents per lane (not for
     // terrain, which ran 7% slower with them)
     constexpr bool PLANES = LANES >= 8 && TPL == 1 && NMAX > 4 && (KIND & KIND_TERRAIN) == 0;
+    // plain envs of the 2- and 4-lane window loops: a lane without an agent
+    // of its own repeats agent l mod n (same cells, roles, output places), so
+    // every lane stores the same words to the same places and no store sits
+    // behind a branch (inactive slots repeat the tile's first env in full)
+    constexpr bool DUP = KIND == KIND_PLAIN && DPP_WINDOW && TPL == 1;
     constexpr int SL = NMAX >= 20 ? 2 : 3;
     constexpr int NP = PAIRS ? NMAX * (NMAX - 1) / 2 : 1;  // agent pairs i < j
 
@@ -978,6 +997,14 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     const int C = (int)((s1 >> 4) & 0xfu);
     const uint32_t flags = (s1 >> 8) & 0xffu, Lep = s1 >> 16;
     const bool collide = (flags & 1u) != 0u;
+    // the agent index each task stands for (its own, or with DUP the agent
+    // it repeats)
+    int aid[TPL];
+#pragma unroll
+    for (int m = 0; m < TPL; ++m) {
+        const int a = l + m * LANES;
+        aid[m] = (DUP && a >= n) ? a % n : a;
+    }
     const bool want_out = C == 4;
     constexpr bool FEAT_OK = KIND != KIND_PLAIN;
     constexpr bool XPL = (KIND & KIND_EXPLORE) != 0;  // every env of the tile explores
@@ -1078,7 +1105,10 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     // positions of this lane's own agents l + m * LANES (agent 0's position for
     // lanes without an agent), kept in registers
     int mine[TPL];
-    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+    if constexpr (DUP)
+        own_positions_ids<NMAX, TPL>(pp, aid, mine);
+    else
+        own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
     if constexpr (PLANES) {
         for (uint32_t i = (uint32_t)l; i < 2u * slot_words; i += LANES) planes[i] = 0u;
         wave_lds_fence();
@@ -1139,11 +1169,11 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
     int rsign[TPL];
 #pragma unroll
     for (int m = 0; m < TPL; ++m) {
-        const int a = l + m * LANES;
+        const int a = l + m * LANES, ai = aid[m];
         mine_live[m] = active && a < n;
-        seeker[m] = a < S;
-        hbit[m] = (a < n && a >= S) ? 1u << a : 0u;
-        rsign[m] = a < S ? 1 : -1;
+        seeker[m] = ai < S;
+        hbit[m] = (ai < n && ai >= S) ? 1u << ai : 0u;
+        rsign[m] = ai < S ? 1 : -1;
     }
     // radio: each task's belief (bit h: the agent knows of hider h)
     uint32_t bel[TPL];
@@ -1172,7 +1202,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 pair_hb[pi] = opp_ij ? 1u << jj : 0u;
 #pragma unroll
                 for (int m = 0; m < TPL; ++m) {
-                    const int a = l + m * LANES;
+                    const int a = aid[m];
                     pinv[m] |= (opp_ij && (a == i || a == jj)) ? 1u << pi : 0u;
                 }
             }
@@ -1216,8 +1246,8 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         GAS float *rew_l[TPL];
 #pragma unroll
         for (int m = 0; m < TPL; ++m) {
-            obs_l[m] = obs_p + (uint32_t)((l + m * LANES) * (C * W + (RAD ? 1 : 0)));
-            rew_l[m] = obs_only ? nullptr : rew_p + (uint32_t)(l + m * LANES);
+            obs_l[m] = obs_p + (uint32_t)(aid[m] * (C * W + (RAD ? 1 : 0)));
+            rew_l[m] = obs_only ? nullptr : rew_p + (uint32_t)aid[m];
         }
         auto store_obs = [&](int m) __attribute__((always_inline)) {
             GAS uint32_t *oa = obs_l[m];
@@ -1232,10 +1262,10 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
         if (obs_only) {
             all_masks<R, W, NMAX, TPL, EX, OC, TER, PL>(slot, H, Wd, pp, l, LANES, mine, n, S,
                                                         want_out, LOS, false, wall, outm, team,
-                                                        opp, seen, cnt, pw, clo, chi, planes, plw);
+                                                        opp, seen, cnt, pw, clo, chi, planes, plw, aid);
 #pragma unroll
             for (int m = 0; m < TPL; ++m)
-                if (mine_live[m]) store_obs(m);
+                if (DUP || mine_live[m]) store_obs(m);
             return;
         }
 
@@ -1518,13 +1548,16 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                     pp[i] = blk ? pp[i] : tgt[i];
                 }
             }
-            own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+            if constexpr (DUP)
+                own_positions_ids<NMAX, TPL>(pp, aid, mine);
+            else
+                own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
             plane_move(pl_from, mine[0]);
 
             // ---- 3 detection at the post-move positions, and the channels
             all_masks<R, W, NMAX, TPL, EX, OC, TER, PL>(slot, H, Wd, pp, l, LANES, mine, n, S,
                                                         want_out, LOS, XP, wall, outm, team, opp,
-                                                        seen, cnt, pw, clo, chi, planes, plw);
+                                                        seen, cnt, pw, clo, chi, planes, plw, aid);
             // The role channels feed only the (predicated) stores, so the
             // compiler would compute them inside the store region; using them
             // here keeps them in the step's main block, where they fill the
@@ -1659,7 +1692,7 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
             // them into the step's dependency chains.
 #pragma unroll
             for (int m = 0; m < TPL; ++m) {
-                if (mine_live[m]) {
+                if (DUP || mine_live[m]) {
                     store_obs(m);
                     *rew_l[m] = rv[m];
                     if (m == 0) *done_p = (uint8_t)d;
@@ -1802,15 +1835,18 @@ __device__ __forceinline__ void step_tile(const Tile &tile, const JobDesc &J, ui
                 }
                 {
                     const int from = mine[0];
-                    own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
+                    if constexpr (DUP)
+                        own_positions_ids<NMAX, TPL>(pp, aid, mine);
+                    else
+                        own_positions<LANES, NMAX, TPL>(pp, l, n, mine);
                     plane_move(from, mine[0]);
                 }
                 all_masks<R, W, NMAX, TPL, EX, OC, TER, PL>(slot, H, Wd, pp, l, LANES, mine, n, S,
                                                             want_out, LOS, false, wall, outm, team,
-                                                            opp, seen, cnt, pw, clo, chi, planes, plw);
+                                                            opp, seen, cnt, pw, clo, chi, planes, plw, aid);
 #pragma unroll
                 for (int m = 0; m < TPL; ++m)
-                    if (mine_live[m]) store_obs(m);
+                    if (DUP || mine_live[m]) store_obs(m);
                 if constexpr (NBR)
                     nbw = gather_blocked<LANES, NMAX, TPL>(l, [&](int m) { return blocked_field<R, W>(wall[m]); });
             }

@@ -1,5 +1,5 @@
-// The two-width kernel of the plain envs of uneven batches (4 lanes per env
-// for up to 4 agents, 16 for up to 10, one launch).
+// The combined kernel of the plain envs of uneven batches (4 lanes per env
+// for up to 4 agents, 8 for up to 8, 16 for up to 10, one launch).
 #include "hase_device.h"
 
 namespace hase {
@@ -9,8 +9,8 @@ hipError_t launch_combo(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs
                         hipStream_t stream)
 {
     if (n_tiles == 0) return hipSuccess;
-    // the 4-lane tiles hold 16 envs per wave: the LDS of the wider slot array
-    const size_t lds = (size_t)16 * (slot_words + MAX_AGENTS) * sizeof(uint32_t);
+    // the widest slot array of the three tile widths
+    const size_t lds = combo_lds_bytes(slot_words);
     hipLaunchKernelGGL((step_kernel_combo<KIND_PLAIN>), dim3(n_tiles), dim3(64), lds, stream, tiles,
                        n_tiles, jobs, job0, K, step_base, slot_words, 0u);
     return hipGetLastError();

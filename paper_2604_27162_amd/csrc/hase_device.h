@@ -2166,12 +2166,11 @@ __global__ __launch_bounds__(64) void step_kernel(const Tile *__restrict__ tiles
 // Variant code of a tile: agent-count bucket * 4 + radius - 1.
 __host__ __device__ constexpr uint32_t variant_code(int bucket, int r) { return (uint32_t)(bucket * 4 + r - 1); }
 
-template <int LANES, int B, int KIND>
-__device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobDesc &J, uint32_t K,
-                                             uint32_t step_base, uint32_t slot_words,
-                                             uint32_t map_words, uint32_t *lds)
+template <int LANES, int NMAX, int KIND>
+__device__ __forceinline__ void mixed_nmax(int r, const Tile &tile, const JobDesc &J, uint32_t K,
+                                           uint32_t step_base, uint32_t slot_words,
+                                           uint32_t map_words, uint32_t *lds)
 {
-    constexpr int NMAX = BUCKET_NMAX[B];
     if constexpr ((NMAX + LANES - 1) / LANES <= 4) {
         switch (r) {
         case 1: step_tile<LANES, NMAX, 1, false, KIND>(tile, J, K, step_base, slot_words, map_words, lds); break;
@@ -2180,6 +2179,14 @@ __device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobD
         default: step_tile<LANES, NMAX, 4, false, KIND>(tile, J, K, step_base, slot_words, map_words, lds); break;
         }
     }
+}
+
+template <int LANES, int B, int KIND>
+__device__ __forceinline__ void mixed_bucket(int r, const Tile &tile, const JobDesc &J, uint32_t K,
+                                             uint32_t step_base, uint32_t slot_words,
+                                             uint32_t map_words, uint32_t *lds)
+{
+    mixed_nmax<LANES, BUCKET_NMAX[B], KIND>(r, tile, J, K, step_base, slot_words, map_words, lds);
 }
 
 // Mixed variants in one launch (uneven batches, feature kinds): each wave
@@ -2217,12 +2224,14 @@ __global__ __launch_bounds__(64) void step_kernel_mixed(const Tile *__restrict__
     }
 }
 
-// Plain envs of an uneven batch in one launch at two widths: the buckets of
-// up to 2 and up to 4 agents at 4 lanes per env (16 envs per wave), those
-// buckets and the one of up to 10 agents at 16 lanes (bit 4 of a tile's
-// variant set). One grid keeps every SIMD busy to the end, where two launch
-// groups of different widths finish at different times, and small envs
-// need not spread over 16 lanes.
+// Plain envs of an uneven batch in one launch at up to three widths: the
+// buckets of up to 2 and up to 4 agents at 4 lanes per env (16 envs per
+// wave), those buckets and the one of up to 10 agents at 16 lanes (bit 4 of
+// a tile's variant set), except that the envs of that bucket with at most 8
+// agents take 8 lanes, one agent per lane (bit 5 set): 8 envs per wave in
+// place of 4, so the batch needs fewer of the heaviest waves. One grid keeps
+// every SIMD busy to the end, where launch groups of different widths
+// finish at different times, and small envs need not spread over 16 lanes.
 template <int KIND>
 __global__ __launch_bounds__(64) void step_kernel_combo(const Tile *__restrict__ tiles,
                                                         uint32_t n_tiles,
@@ -2237,7 +2246,9 @@ __global__ __launch_bounds__(64) void step_kernel_combo(const Tile *__restrict__
     if (tile.count == 0u || (job0.group != ALL_GROUPS && (tile.variant >> 8) != job0.group)) return;
     const JobDesc J = jobs ? jobs[tile.job] : job0;
     const int bucket = (int)((tile.variant >> 2) & 3u), r = (int)(tile.variant & 3u) + 1;
-    if ((tile.variant >> 4) & 1u) {
+    if ((tile.variant >> 5) & 1u) {
+        mixed_nmax<8, COMBO_MID_NMAX, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds);
+    } else if ((tile.variant >> 4) & 1u) {
         switch (bucket) {
         case 0: mixed_bucket<16, 0, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;
         case 1: mixed_bucket<16, 1, KIND>(r, tile, J, K, step_base, slot_words, map_words, lds); break;

@@ -184,8 +184,21 @@ hipError_t launch_mixed(int lanes, int kind, const Tile *tiles, uint32_t n_tiles
 
 // The plain envs of an uneven batch whose buckets take 4 lanes per env (up
 // to 4 agents) and 16 (up to 10 agents) in one launch: tiles of 16 lanes per
-// env have bit 4 of their variant set (hase_combo.hip).
+// env have bit 4 of their variant set; the envs of the 10-agent bucket with
+// at most COMBO_MID_NMAX agents run at 8 lanes per env, one agent per lane,
+// in tiles with bit 5 set (hase_combo.hip).
 constexpr uint32_t COMBO_WIDE = 16u;
+constexpr uint32_t COMBO_MID = 32u;
+constexpr int COMBO_MID_NMAX = 8;
+// LDS bytes per wave of that launch: 16 env slots for the 4-lane tiles, or 8
+// slots with the two agent planes each for the 8-lane tiles (the 16-lane
+// tiles' 4 such slots need less than either).
+inline size_t combo_lds_bytes(uint32_t slot_words)
+{
+    const size_t narrow = (size_t)16 * (slot_words + MAX_AGENTS);
+    const size_t mid = (size_t)8 * (3 * (size_t)slot_words + MAX_AGENTS);
+    return (narrow > mid ? narrow : mid) * sizeof(uint32_t);
+}
 hipError_t launch_combo(const Tile *tiles, uint32_t n_tiles, const JobDesc *jobs,
                         const JobDesc &job0, uint32_t K, uint32_t step_base, uint32_t slot_words,
                         hipStream_t stream);

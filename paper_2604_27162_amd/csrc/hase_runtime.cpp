@@ -315,50 +315,58 @@ int build_tiles(hase_batch *b)
     std::vector<Tile> tiles;
     std::vector<Variant> vars;
     // plain envs whose bucket takes 4 lanes (up to 4 agents) or 16 (up to 10)
-    // go to one two-width launch when both widths occur
+    // go to one launch when more than one width occurs; there the 10-agent
+    // bucket's envs with at most COMBO_MID_NMAX agents take 8 lanes
     auto in_combo = [&](int bk) {
         return bk < N_BUCKETS - 1 && ((b->lanes[bk] == 4 && bk <= 1) || b->lanes[bk] == 16);
     };
-    bool has4 = false, has16 = false;
-    for (const hase_env_spec &s : p.specs) {
+    auto combo_width = [&](const hase_env_spec &s) -> uint32_t {
         const int bk = bucket_of(s.n_agents);
-        if (env_kind(s.flags) == KIND_PLAIN && in_combo(bk)) (b->lanes[bk] == 4 ? has4 : has16) = true;
+        if (b->lanes[bk] == 4) return 4;
+        return (bk == 2 && s.n_agents <= COMBO_MID_NMAX) ? 8 : 16;
+    };
+    bool has4 = false, has8 = false, has16 = false;
+    for (const hase_env_spec &s : p.specs) {
+        if (env_kind(s.flags) != KIND_PLAIN || !in_combo(bucket_of(s.n_agents))) continue;
+        const uint32_t w = combo_width(s);
+        (w == 4 ? has4 : w == 8 ? has8 : has16) = true;
     }
-    const bool combo = has4 && has16;
+    const bool combo = (int)has4 + (int)has8 + (int)has16 >= 2;
     if (combo) {
         Variant grp;
         grp.lanes = 4;  // LDS of 16 env slots per wave
         grp.kind = KIND_PLAIN;
         grp.mixed = grp.combo = true;
         grp.tile0 = (uint32_t)tiles.size();
-        for (uint32_t L : {4u, 16u}) {
+        for (uint32_t L : {4u, 8u, 16u}) {
             for (int bk = 0; bk < N_BUCKETS; ++bk) {
-                if (b->lanes[bk] != L || !in_combo(bk)) continue;
+                if (!in_combo(bk)) continue;
                 for (int r = 1; r <= PAD; ++r) {
                     const uint32_t base = (uint32_t)perm.size();
                     for (uint32_t e = 0; e < N; ++e) {
                         const hase_env_spec &s = p.specs[e];
                         if (bucket_of(s.n_agents) == bk && s.view_radius == r &&
-                            env_kind(s.flags) == KIND_PLAIN) {
+                            env_kind(s.flags) == KIND_PLAIN && combo_width(s) == L) {
                             perm.push_back(e);
                             grp.slot_words = std::max(grp.slot_words, (uint32_t)board_words(s.height, 1));
                         }
                     }
                     const uint32_t cnt = (uint32_t)perm.size() - base, E = 64u / L;
+                    const uint32_t width_bits = L == 16 ? COMBO_WIDE : L == 8 ? COMBO_MID : 0u;
                     for (uint32_t i = 0; i < cnt; i += E) {
                         Tile t;
                         t.job = 0;
                         t.env0 = base + i;
                         t.count = std::min<uint32_t>(E, cnt - i);
-                        t.variant = (uint32_t)(bk * 4 + r - 1) | (L == 16 ? COMBO_WIDE : 0u);
+                        t.variant = (uint32_t)(bk * 4 + r - 1) | width_bits;
                         tiles.push_back(t);
                     }
                 }
             }
         }
         grp.n_tiles = (uint32_t)tiles.size() - grp.tile0;
-        if ((size_t)16 * (grp.slot_words + MAX_AGENTS) * 4 > 65536)
-            return fail(HASE_EINVAL, "tiling: the two-width launch needs more than 64 KiB of LDS per wave");
+        if (combo_lds_bytes(grp.slot_words) > 65536)
+            return fail(HASE_EINVAL, "tiling: the combined launch needs more than 64 KiB of LDS per wave");
         vars.push_back(grp);
     }
     const uint32_t lane_order[] = {1, 2, 4, 8, 16};
@@ -1181,8 +1189,9 @@ int hase_step_multi(const hase_step_io *io, uint32_t n, uint32_t n_steps, void *
                     // a request whose boards would push the group past 64 KiB of
                     // LDS per wave starts a launch group of its own
                     const uint32_t slot = std::max(g.slot, v.slot_words), map = std::max(g.map, v.map_words);
-                    if ((size_t)(64u / L) * (slot + MAX_AGENTS + map) * 4 > 65536 &&
-                        tiles.size() > g.tile0) {
+                    const size_t need = combo ? combo_lds_bytes(slot)
+                                              : (size_t)(64u / L) * (slot + MAX_AGENTS + map) * 4;
+                    if (need > 65536 && tiles.size() > g.tile0) {
                         close_group();
                         open_group();
                     }

@@ -55,6 +55,33 @@ def test_step_multi_matches_separate_batches():
             assert torch.equal(got, want)
 
 
+def test_step_multi_uneven_requests_match_oracle():
+    """Two uneven plain requests in one multi-batch step: their combined
+    launches (4-, 8- and 16-lane tiles of both requests in one grid) give
+    each request the oracle's outputs."""
+    reqs = [(wl.workload_specs("uneven8k", 1400)[:157], 21, 30),
+            ([s for s in wl.workload_specs("uneven8k", 900)[400:] if s["n"] >= 5][:71], 22, 19)]
+    bs = []
+    for specs, seed, _ in reqs:
+        b = hase.HaseBatch(specs, device=DEV)
+        b.reset(seed)
+        bs.append(b)
+    outs = [b.alloc_outputs(k) for b, (_, _, k) in zip(bs, reqs)]
+    ws = torch.empty(hase.multi_workspace_bytes(bs), dtype=torch.uint8, device=DEV)
+    stream = torch.cuda.current_stream()
+    items = [(b, k, 0, None, *out) for b, (_, _, k), out in zip(bs, reqs, outs)]
+    hase.step_multi(items, 30, ws, stream)
+    torch.cuda.synchronize()
+    for (specs, seed, k), (go, gr, gd), b in zip(reqs, outs, bs):
+        ob = o.OracleBatch(specs)
+        ob.reset(seed)
+        oo, orr, od = ob.step(k)
+        assert np.array_equal(go.cpu().numpy().view(np.uint32).reshape(oo.shape), oo)
+        assert np.array_equal(gr.cpu().numpy().view(np.uint32).reshape(orr.shape), orr.view(np.uint32))
+        assert np.array_equal(gd.cpu().numpy().reshape(od.shape), od)
+        b.close()
+
+
 def test_server_alone_vs_mix_bit_exact():
     """Requests served together in the arena, some admitted while others
     run and into slots others left, equal the same requests run alone and

@@ -69,7 +69,7 @@ int bucket_of(int n)
 const uint32_t DEFAULT_LANES[N_BUCKETS] = {4, 4, 16, 16};
 
 // Default tiling of a batch: the built-in lanes per bucket. A batch of plain
-// envs only keeps them (its 4- and 16-lane envs share one two-width launch);
+// envs only keeps them (its 4- and 16-lane envs share one combined launch);
 // otherwise, when the buckets with the widest built-in lanes hold at least
 // half of the batch's agents, every bucket takes those lanes, so the whole
 // batch is one launch group (one kernel keeps all SIMDs busy to the end,
@@ -229,12 +229,12 @@ struct Variant {
     // mixed: the per-tile variant switch (the feature kinds have only that
     // kernel); xpl: an env explores (LDS discovery maps of map_words); big:
     // the bucket of up to 20 agents, whose mixed kernel is its own; combo:
-    // the two-width launch of plain envs at 4 and 16 lanes
+    // the combined launch of plain envs at 4, 8 and 16 lanes
     bool mixed = false, xpl = false, big = false, combo = false;
     uint32_t tile0 = 0, n_tiles = 0, slot_words = 0, map_words = 0;
 };
 
-// lanes x kinds x (big or not) launches at most, plus the two-width one,
+// lanes x kinds x (big or not) launches at most, plus the combined one,
 // each on its own stream when forked
 constexpr int MAX_LAUNCHES = 5 * N_KINDS * 2 + 1;
 

@@ -146,7 +146,7 @@ def test_every_tiling_matches(lanes):
 
 @pytest.mark.parametrize("lanes", [[4, 4, 16, 16], [16, 4, 16, 8], [4, 16, 16, 16]])
 def test_two_width_launch_matches(lanes):
-    """Plain envs at 4 and 16 lanes per env in one two-width launch (the
+    """Plain envs at 4 and 16 lanes per env in one combined launch (the
     default tiling of uneven plain batches), beside a 20-agent bucket."""
     specs = wl.workload_specs("uneven8k", 411) + [EDGE_SPECS["max_agents_64x64"]] * 7
     run_pair(specs, seed=57, steps=150, lanes=lanes)

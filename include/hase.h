@@ -346,11 +346,10 @@ int hase_set_state(hase_batch *b, const hase_host_state *in);
  * default: 4, 4, 16, 16 lanes, except that when the buckets with the widest
  * of those hold at least half of the batch's agents, every bucket present
  * takes the widest (one launch group); hase_create starts from the
- * default. Plain envs whose buckets take 4 and 16 lanes share one launch;
- * there, when more than one width occurs, the envs of bucket 2 with at most
- * 8 agents run at 8 lanes per env (one agent per lane) while bucket 2 reads
- * 16. Results never depend on the tiling. Rebuilds the tile table
- * (synchronously) and drops cached graphs.
+ * default. Plain envs whose buckets take 4 and 16 lanes share one launch,
+ * in which the envs of bucket 2 with at most 8 agents run at 8 lanes per env
+ * (one agent per lane) while bucket 2 reads 16. Results never depend on the
+ * tiling. Rebuilds the tile table (synchronously) and drops cached graphs.
  */
 #define HASE_N_BUCKETS 4
 int hase_set_tiling(hase_batch *b, const uint32_t lanes[HASE_N_BUCKETS]);

@@ -315,8 +315,10 @@ int build_tiles(hase_batch *b)
     std::vector<Tile> tiles;
     std::vector<Variant> vars;
     // plain envs whose bucket takes 4 lanes (up to 4 agents) or 16 (up to 10)
-    // go to one launch when more than one width occurs; there the 10-agent
-    // bucket's envs with at most COMBO_MID_NMAX agents take 8 lanes
+    // go to one launch when both widths occur or when some of them have 5 to
+    // COMBO_MID_NMAX agents: those take 8 lanes there, one agent per lane, so
+    // a wave holds 8 of them instead of 4 (half the waves at equal time per
+    // wave)
     auto in_combo = [&](int bk) {
         return bk < N_BUCKETS - 1 && ((b->lanes[bk] == 4 && bk <= 1) || b->lanes[bk] == 16);
     };
@@ -331,7 +333,7 @@ int build_tiles(hase_batch *b)
         const uint32_t w = combo_width(s);
         (w == 4 ? has4 : w == 8 ? has8 : has16) = true;
     }
-    const bool combo = (int)has4 + (int)has8 + (int)has16 >= 2;
+    const bool combo = has8 || (has4 && has16);
     if (combo) {
         Variant grp;
         grp.lanes = 4;  // LDS of 16 env slots per wave

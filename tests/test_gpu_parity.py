@@ -153,12 +153,12 @@ def test_two_width_launch_matches(lanes):
     run_pair(specs, seed=58, steps=40, lanes=lanes, mode=hase.PER_LAUNCH)
 
 
-@pytest.mark.parametrize("agents", [(1, 10), (5, 10), (1, 8)])
+@pytest.mark.parametrize("agents", [(1, 10), (5, 10), (1, 8), (5, 8)])
 def test_three_width_launch_matches(agents):
     """The combined launch with envs of the 10-agent bucket that have at most
     8 agents at 8 lanes per env: all three widths, only 8 and 16, only 4 and
-    8. Counts are ragged for every width and radius; 16x16 grids with many
-    agents end episodes often, so respawns run in every tile."""
+    8, only 8. Counts are ragged for every width and radius; 16x16 grids with
+    many agents end episodes often, so respawns run in every tile."""
     lo, hi = agents
     specs = [s for s in wl.workload_specs("uneven8k", 1400) if lo <= s["n"] <= hi][:333]
     specs += [wl.spec(16, 16, n, r, 4, 20, L=40) for n in range(max(lo, 5), min(hi, 8) + 1)

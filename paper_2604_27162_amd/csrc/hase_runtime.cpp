@@ -263,7 +263,7 @@ struct hase_batch {
     // cells and cap_n agents; ranges of slots admitted by hase_reset_range
     struct Range {
         uint32_t count, job, kind, lanes, n_tiles, slot_words, map_words;
-        bool big;
+        bool big, mid;  // mid: 8-lane tiles of the combined kernel
     };
     bool arena = false;
     uint32_t cap_h = 0, cap_w = 0, cap_n = 0;
@@ -293,6 +293,14 @@ struct hase_batch {
 };
 
 namespace {
+
+// Launch group of an arena range's tiles (bits 8 and up of their variant):
+// the kernel's group code, plus bit 17 for the 8-lane tiles that the
+// combined kernel runs.
+uint32_t arena_group(int kind, int lanes, bool big, bool mid)
+{
+    return group_code(kind, lanes, big) | (mid ? 1u << 17 : 0u);
+}
 
 void drop_graphs(hase_batch *b)
 {
@@ -1428,6 +1436,11 @@ int hase_reset_range(hase_batch *b, uint32_t first_slot, uint32_t count, const h
     if (!variant_supported((int)lanes, BUCKET_NMAX[bk]) ||
         (size_t)(64u / lanes) * (slot_words + MAX_AGENTS + mwl) * 4 > 65536)
         return fail(HASE_EINVAL, "no tiling fits this spec in LDS");
+    // plain envs of 5 to COMBO_MID_NMAX agents take the combined kernel's
+    // 8-lane tiles, one agent per lane (8 envs per wave instead of 4)
+    const bool mid = kind == KIND_PLAIN && bk == 2 && lanes == 16 && s.n_agents <= COMBO_MID_NMAX &&
+                     combo_lds_bytes(slot_words) <= 65536;
+    if (mid) lanes = 8;
     const uint32_t E = 64u / lanes;
     const uint32_t w = (uint32_t)words_per_channel(s.view_radius);
     const uint32_t obs_env = s.n_agents * (s.n_channels * w + ((s.flags & HASE_RADIO) ? 1u : 0u));
@@ -1471,7 +1484,8 @@ int hase_reset_range(hase_batch *b, uint32_t first_slot, uint32_t count, const h
     a.env_id_base = env_id_base;
     a.lanes = lanes;
     const bool big = bk == N_BUCKETS - 1;
-    a.variant = (uint32_t)(bk * 4 + s.view_radius - 1) | (group_code(kind, (int)lanes, big) << 8);
+    a.variant = (uint32_t)(bk * 4 + s.view_radius - 1) | (mid ? COMBO_MID : 0u) |
+                (arena_group(kind, (int)lanes, big, mid) << 8);
     if (s.flags & HASE_TERRAIN) {
         a.terr_words[0] = s.water_pct | ((uint32_t)s.mud_pct << 8) | ((uint32_t)s.stuck_pct << 16);
         for (int k = 0; k < 9; ++k) a.terr_words[1 + k / 4] |= (uint32_t)s.speed_pct[k] << (8 * (k % 4));
@@ -1492,12 +1506,16 @@ int hase_reset_range(hase_batch *b, uint32_t first_slot, uint32_t count, const h
         JobDesc j0 = j;
         j0.obs = out->obs0;
         j0.obs_stride = 0;
-        HIP_TRY(launch_mixed((int)lanes, kind, b->at<Tile>(r.tiles) + first_slot, n_tiles, nullptr, j0,
-                             0, 0, slot_words, mwl, big, b->stream));
+        if (mid)
+            HIP_TRY(launch_combo(b->at<Tile>(r.tiles) + first_slot, n_tiles, nullptr, j0, 0, 0, slot_words,
+                                 b->stream));
+        else
+            HIP_TRY(launch_mixed((int)lanes, kind, b->at<Tile>(r.tiles) + first_slot, n_tiles, nullptr,
+                                 j0, 0, 0, slot_words, mwl, big, b->stream));
     }
     b->free_jobs.pop_back();
     b->ranges[first_slot] =
-        hase_batch::Range{count, job, (uint32_t)kind, lanes, n_tiles, slot_words, mwl, big};
+        hase_batch::Range{count, job, (uint32_t)kind, lanes, n_tiles, slot_words, mwl, big, mid};
     return HASE_OK;
 }
 
@@ -1542,16 +1560,16 @@ int hase_step_resident(hase_batch *b, uint32_t n_steps)
     // ones); groups run concurrently on forked streams
     struct G {
         uint32_t kind, lanes, extent, slot, map;
-        bool big;
+        bool big, mid;
     };
     std::vector<G> groups;
     for (const auto &kv : b->ranges) {
         const hase_batch::Range &rg = kv.second;
         G *g = nullptr;
         for (G &x : groups)
-            if (x.kind == rg.kind && x.lanes == rg.lanes && x.big == rg.big) g = &x;
+            if (x.kind == rg.kind && x.lanes == rg.lanes && x.big == rg.big && x.mid == rg.mid) g = &x;
         if (!g) {
-            groups.push_back(G{rg.kind, rg.lanes, 0u, rg.slot_words, rg.map_words, rg.big});
+            groups.push_back(G{rg.kind, rg.lanes, 0u, rg.slot_words, rg.map_words, rg.big, rg.mid});
             g = &groups.back();
         }
         g->extent = std::max(g->extent, kv.first + rg.n_tiles);
@@ -1568,14 +1586,17 @@ int hase_step_resident(hase_batch *b, uint32_t n_steps)
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const G &g = groups[gi];
         JobDesc filter{};
-        filter.group = group_code((int)g.kind, (int)g.lanes, g.big);
+        filter.group = arena_group((int)g.kind, (int)g.lanes, g.big, g.mid);
         hipStream_t st = b->stream;
         if (fork && gi > 0) {
             HIP_TRY(hipStreamWaitEvent(b->side[gi], b->fork_ev, 0));
             st = b->side[gi];
         }
-        HIP_TRY(launch_mixed((int)g.lanes, (int)g.kind, tiles, g.extent, jobs, filter, n_steps, 0,
-                             g.slot, g.map, g.big, st));
+        if (g.mid)
+            HIP_TRY(launch_combo(tiles, g.extent, jobs, filter, n_steps, 0, g.slot, st));
+        else
+            HIP_TRY(launch_mixed((int)g.lanes, (int)g.kind, tiles, g.extent, jobs, filter, n_steps, 0,
+                                 g.slot, g.map, g.big, st));
         if (fork && gi > 0) {
             HIP_TRY(hipEventRecord(b->join_ev[gi], st));
             HIP_TRY(hipStreamWaitEvent(b->stream, b->join_ev[gi], 0));

@@ -21,6 +21,7 @@ SPECS = {
     "terrain": wl.with_terrain(wl.spec(20, 20, 6, 2, 4, 10)),
     "radio": wl.spec(16, 24, 7, 4, 4, 10, flags=wl.DEFAULT_FLAGS | wl.RADIO),
     "short_episodes": wl.spec(12, 12, 4, 2, 4, 15, L=9),
+    "mid8": wl.spec(16, 16, 8, 3, 4, 20, L=30),
 }
 
 
@@ -49,7 +50,7 @@ def test_ranges_match_batches_and_oracle():
     plan = [("plain", 0, 150, 11, 40, 0), ("multi", 150, 37, 12, 100, 5),
             ("big", 200, 21, 13, 77, 0), ("explore_los", 230, 45, 14, 64, 1000),
             ("terrain", 290, 33, 15, 50, 7), ("radio", 330, 29, 16, 45, 3),
-            ("short_episodes", 400, 70, 17, 90, 0)]
+            ("short_episodes", 400, 70, 17, 90, 0), ("mid8", 480, 53, 18, 100, 9)]
     outs = {}
     for name, first, count, seed, steps, base in plan:
         print(f"case: admit {name} at {first} x {count}", flush=True)
@@ -62,14 +63,15 @@ def test_ranges_match_batches_and_oracle():
     for name, first, count, seed, steps, base in plan:
         assert ar.range_error(first) == -1
         check_range(name, outs[name], count, seed, steps, base)
-    # one range against the oracle as well
-    name, first, count, seed, steps, base = plan[1]
-    ob = o.OracleBatch([SPECS[name]] * count, env_id_base=base)
-    assert np.array_equal(hase.as_u32(outs[name]["obs0"]), ob.reset(seed))
-    oo, orr, od = ob.step(steps)
-    assert np.array_equal(hase.as_u32(outs[name]["obs"]), oo)
-    assert np.array_equal(outs[name]["rew"].cpu().numpy().view(np.uint32), orr.view(np.uint32))
-    assert np.array_equal(outs[name]["done"].cpu().numpy(), od)
+    # ranges of 16-lane tiles and of 8-lane tiles (5 and 8 agents) against
+    # the oracle as well
+    for name, first, count, seed, steps, base in (plan[1], plan[2], plan[-1]):
+        ob = o.OracleBatch([SPECS[name]] * count, env_id_base=base)
+        assert np.array_equal(hase.as_u32(outs[name]["obs0"]), ob.reset(seed)), name
+        oo, orr, od = ob.step(steps)
+        assert np.array_equal(hase.as_u32(outs[name]["obs"]), oo), name
+        assert np.array_equal(outs[name]["rew"].cpu().numpy().view(np.uint32), orr.view(np.uint32)), name
+        assert np.array_equal(outs[name]["done"].cpu().numpy(), od), name
     ar.close()
 
 

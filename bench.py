@@ -251,6 +251,9 @@ def main():
                     help="time the runs only (profiling: no other launch of the step kernel)")
     ap.add_argument("--only-per-launch", action="store_true",
                     help="time only the run with one kernel launch per env-step (profiling)")
+    ap.add_argument("--int8-actions", action="store_true",
+                    help="the timed runs take external int8 actions resident in HBM (with "
+                         "--only-runs: profiling of that leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-maps", action="store_true",
                     help="exploring workloads: skip the per-step discovery-map output")
@@ -315,9 +318,11 @@ def main():
                           "workload": args.workload}), flush=True)
         g.close()
         return
-    g.prepare(obs, rew, done, R, maps=mp, state=st)
+    xa = (torch.randint(0, 5, (R, agents), dtype=torch.int8, device="cuda:0")
+          if args.int8_actions else None)
+    g.prepare(obs, rew, done, R, actions=xa, maps=mp, state=st)
     for _ in range(W):
-        g.step_into(obs, rew, done, R, maps=mp, state=st)
+        g.step_into(obs, rew, done, R, actions=xa, maps=mp, state=st)
     torch.cuda.synchronize()
 
     # ---- K runs back to back, an event between consecutive runs
@@ -326,7 +331,7 @@ def main():
     t0 = time.perf_counter()
     evs[0].record(stream)
     for k in range(K):
-        g.step_into(obs, rew, done, R, maps=mp, state=st)
+        g.step_into(obs, rew, done, R, actions=xa, maps=mp, state=st)
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall_s = time.perf_counter() - t0
@@ -335,7 +340,8 @@ def main():
     mean_ms = total_ms / K
     value = agents * R * K / (total_ms / 1e3)
 
-    alg_bytes = R * out_bytes_per_step(specs, maps_on, state=state_on) + state_bytes_per_launch(specs)
+    alg_bytes = (R * out_bytes_per_step(specs, maps_on, actions=xa is not None, state=state_on) +
+                 state_bytes_per_launch(specs))
     achieved = alg_bytes / (mean_ms / 1e3) / 1e9
     line = {
         "metric": METRIC,
@@ -354,12 +360,13 @@ def main():
                    "n_envs": n_envs, "agents": agents, "env_steps_per_bench_step": R,
                    "launch": "persistent: one kernel launch per run (per lanes group)",
                    "lanes_per_env": g.get_tiling(), "map_output": maps_on,
-                   "true_state_output": state_on},
+                   "true_state_output": state_on,
+                   "actions": "external int8" if xa is not None else "counter generator"},
         "env_steps_per_s": n_envs * R * K / (total_ms / 1e3),
         "run_ms": spread(run_ms),
         "wall_s_timed_region": wall_s,
     }
-    traffic = traffic_from_profiles(args.workload, R)
+    traffic = traffic_from_profiles(args.workload + ("_int8" if xa is not None else ""), R)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "step kernel (persistent, one launch per run)",

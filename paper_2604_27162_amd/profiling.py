@@ -22,7 +22,10 @@ that bench.py reports it only while the kernel is unchanged.
 With --per-launch, one kernel trace of bench.py --only-per-launch (one
 launch per env-step) instead, summarised to
 profiles/step_kernel_<workload>_per_launch.md: kernel time per launch
-against the gaps between launches.
+against the gaps between launches. With --int8, the same passes over runs
+with external int8 actions (bench.py --int8-actions), summarised to
+profiles/step_kernel_<workload>_int8.md and keyed <workload>_int8 in
+traffic.json.
 """
 from __future__ import annotations
 
@@ -75,18 +78,21 @@ def main(argv=None):
     ap.add_argument("--collect-only", action="store_true", help="run rocprofv3 only")
     ap.add_argument("--summarize-only", action="store_true",
                     help="only summarise raw output collected earlier")
+    ap.add_argument("--int8", action="store_true",
+                    help="profile runs with external int8 actions resident in HBM")
     ap.add_argument("--per-launch", action="store_true",
                     help="profile the run with one kernel launch per env-step instead "
                          "(kernel trace only)")
     args = ap.parse_args(argv)
     if args.per_launch:
         return per_launch(args)
-    raw = os.path.abspath(args.raw or os.path.join(ROOT, "rocprof_raw", f"profile_{args.workload}"))
+    tag = args.workload + ("_int8" if args.int8 else "")
+    raw = os.path.abspath(args.raw or os.path.join(ROOT, "rocprof_raw", f"profile_{tag}"))
     os.makedirs(raw, exist_ok=True)
     os.makedirs(args.out, exist_ok=True)
     py = sys.executable
     bench = [py, os.path.join(ROOT, "bench.py"), "--workload", args.workload, "--only-runs",
-             "--no-cpu-baseline"]
+             "--no-cpu-baseline"] + (["--int8-actions"] if args.int8 else [])
     timed = bench + ["--steps", "5", "--warmup", "1"]
     one = bench + ["--steps", "1", "--warmup", "0"]
     copy = [py, os.path.join(ROOT, "bench.py"), "--copy-probe", str(COPY_BYTES)]
@@ -137,22 +143,23 @@ def main(argv=None):
     maps = any(s["flags"] & bench.EXPLORE for s in specs)
     # bench.py writes the discovery maps and the true state of exploring
     # workloads by default
-    alg = (steps * bench.out_bytes_per_step(specs, maps, state=maps) +
+    alg = (steps * bench.out_bytes_per_step(specs, maps, actions=args.int8, state=maps) +
            bench.state_bytes_per_launch(specs))
     khash = bench.kernel_source_hash()
     waves = sq["SQ_WAVES"] or 1.0
 
     tj = os.path.join(args.out, "traffic.json")
     d = json.load(open(tj)) if os.path.exists(tj) else {}
-    d[args.workload] = {"kernel_hash": khash, "steps": steps, "hbm_bytes_per_launch": traffic,
-                        "fetch_kib": fetch_kib, "write_kib": write_kib, "scale_fetch": sf,
-                        "scale_write": sw, "alg_bytes_per_launch": alg, "kernel": kname,
-                        "launch_ns_avg": avg_ns, "sq": sq}
+    d[tag] = {"kernel_hash": khash, "steps": steps, "hbm_bytes_per_launch": traffic,
+              "fetch_kib": fetch_kib, "write_kib": write_kib, "scale_fetch": sf,
+              "scale_write": sw, "alg_bytes_per_launch": alg, "kernel": kname,
+              "launch_ns_avg": avg_ns, "sq": sq}
     json.dump(d, open(tj, "w"), indent=1, sort_keys=True)
 
-    md = os.path.join(args.out, f"step_kernel_{args.workload}.md")
+    md = os.path.join(args.out, f"step_kernel_{tag}.md")
     with open(md, "w") as f:
-        f.write(f"# step kernel, workload {args.workload}, {steps} steps per launch\n\n")
+        f.write(f"# step kernel, workload {args.workload}, {steps} steps per launch"
+                f"{', external int8 actions' if args.int8 else ''}\n\n")
         f.write(f"Device sources hash: `{khash}`\n\n## Commands (run from /tmp)\n\n")
         for name, cmd in cmds.items():
             rel = [c.replace(ROOT + "/", "").replace(raw, "<raw>").replace(py, "python3")
